@@ -1,0 +1,464 @@
+"""FP64 CPU oracle for the even-odd preconditioned Mobius domain-wall
+operator and the multi-splitting preconditioned CG (MSPCG) built on it.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module.  It shares no code
+with the HIP library (``paper_2104_05615_amd``) and never imports it.
+
+Every function writes out the plain definition it follows (cited by section
+and equation of arxiv 2104.05615) in FP64, without blocking, fusion or
+reordering beyond what the definition states.  The Wilson hopping term is a C
+loop (``hop.c``); all fifth-dimension operators are dense
+``(4 Ls) x (4 Ls)`` complex matrices in spin x s space built from their
+definitions, applied with a matrix product.
+
+Readings taken where the paper is silent (each is listed in the design doc):
+
+* gamma matrices: chiral basis, gamma_5 = diag(1, 1, -1, -1);
+* periodic boundaries in all four directions;
+* the fifth-dimension operators follow the Mobius construction the paper
+  cites for details: with the chirality-twisted shift
+  ``(P~ psi)(s) = P_- psi(s+1) + P_+ psi(s-1)``,
+  ``psi(Ls) = -mf psi(0)``, ``psi(-1) = -mf psi(Ls-1)``,
+  ``M_5 = (b(4 - M5) + 1) + (c(4 - M5) - 1) P~`` and
+  ``M_phi = -(b + c P~)/2``, so that ``M^4 = D^w M_phi`` as written in the paper;
+* inner CG: per-subdomain scalars, fixed k iterations, no early exit;
+* outer MSPCG: Polak-Ribiere beta, plain CG: Fletcher-Reeves beta, stop on
+  the L2 residual relative to ||b||.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_hop.so")
+
+# --------------------------------------------------------------------------
+# C hopping term
+# --------------------------------------------------------------------------
+
+
+def build_hop_library(force: bool = False) -> str:
+    """Compile ``hop.c`` with gcc (OpenMP) into ``oracle/_hop.so``."""
+    src = os.path.join(_HERE, "hop.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fcx-limited-range", "-fopenmp", "-fPIC", "-shared",
+                               src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _hop_lib():
+    global _lib
+    if _lib is None:
+        build_hop_library()
+        # idle OpenMP workers must not spin: they would starve the BLAS
+        # threads that apply the fifth-dimension matrices
+        os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+        os.environ.setdefault("GOMP_SPINCOUNT", "0")
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.oracle_wilson_hop.restype = None
+        lib.oracle_wilson_hop.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int] * 7
+        _lib = lib
+    return _lib
+
+
+# --------------------------------------------------------------------------
+# gamma matrices (Sec. 2.2 uses gamma_mu in D^w; basis not given -> chiral)
+# --------------------------------------------------------------------------
+
+_S1 = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_S2 = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_S3 = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+_I2 = np.eye(2, dtype=np.complex128)
+_Z2 = np.zeros((2, 2), dtype=np.complex128)
+
+
+def _chiral_gamma(sig):
+    return np.block([[_Z2, -1j * sig], [1j * sig, _Z2]])
+
+
+GAMMA = np.ascontiguousarray(np.stack([
+    _chiral_gamma(_S1),                    # x
+    _chiral_gamma(_S2),                    # y
+    _chiral_gamma(_S3),                    # z
+    np.block([[_Z2, _I2], [_I2, _Z2]]),    # t
+]))
+GAMMA5 = GAMMA[0] @ GAMMA[1] @ GAMMA[2] @ GAMMA[3]
+P_PLUS = 0.5 * (np.eye(4) + GAMMA5)
+P_MINUS = 0.5 * (np.eye(4) - GAMMA5)
+
+
+# --------------------------------------------------------------------------
+# geometry
+# --------------------------------------------------------------------------
+
+
+def parity_coords(dims, parity):
+    """(x, y, z, t) of the sites of one parity in single-parity order (lex/2)."""
+    X, Y, Z, T = dims
+    vh = X * Y * Z * T // 2
+    lex0 = 2 * np.arange(vh)
+    x0 = lex0 % X
+    y = (lex0 // X) % Y
+    z = (lex0 // (X * Y)) % Z
+    t = lex0 // (X * Y * Z)
+    x = x0 + ((y + z + t + parity) & 1)
+    return np.stack([x, y, z, t], axis=1)
+
+
+def wilson_hop(U, psi, out_parity, dagger=False):
+    """D^w (or its adjoint) from parity ``1 - out_parity`` to ``out_parity``.
+
+    Sec. 2.2, definition of D^w_{x,y}.  ``psi``: ``[..][Ls][V/2][4][3]``; leading
+    batch axes are folded into the fifth dimension, on which D^w is diagonal."""
+    T, Z, Y, X = U.shape[:4]
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    shape = psi.shape
+    vh = shape[-3]
+    assert shape[-2:] == (4, 3) and vh == X * Y * Z * T // 2
+    ls_tot = int(np.prod(shape[:-3])) if len(shape) > 3 else 1
+    out = np.empty_like(psi)
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    _hop_lib().oracle_wilson_hop(U.ctypes.data, GAMMA.ctypes.data, psi.ctypes.data,
+                                 out.ctypes.data, X, Y, Z, T, ls_tot,
+                                 int(out_parity), 1 if dagger else 0)
+    return out
+
+
+# --------------------------------------------------------------------------
+# fifth-dimension operators: dense (Ls,4,Ls,4) complex matrices
+# --------------------------------------------------------------------------
+
+
+def ptilde(Ls, mf):
+    """Chirality-twisted shift P~ with the -mf wall coupling:
+    (P~ psi)(s) = P_- psi(s+1) + P_+ psi(s-1), psi(Ls) = -mf psi(0),
+    psi(-1) = -mf psi(Ls-1).  Indexed [s, alpha, t, beta]."""
+    P = np.zeros((Ls, 4, Ls, 4), dtype=np.complex128)
+    for s in range(Ls):
+        if s + 1 < Ls:
+            P[s, :, s + 1, :] += P_MINUS
+        else:
+            P[s, :, 0, :] += -mf * P_MINUS
+        if s - 1 >= 0:
+            P[s, :, s - 1, :] += P_PLUS
+        else:
+            P[s, :, Ls - 1, :] += -mf * P_PLUS
+    return P
+
+
+def _eye5(Ls):
+    return np.eye(4 * Ls, dtype=np.complex128).reshape(Ls, 4, Ls, 4)
+
+
+def m5_matrix(Ls, b, c, M5, mf):
+    """M_5 = (b(4 - M5) + 1) 1 + (c(4 - M5) - 1) P~ (Mobius, diagonal in 4D)."""
+    a0 = b * (4.0 - M5) + 1.0
+    a1 = c * (4.0 - M5) - 1.0
+    return a0 * _eye5(Ls) + a1 * ptilde(Ls, mf)
+
+
+def mphi_matrix(Ls, b, c, mf):
+    """M_phi = -(b 1 + c P~)/2, so that M^4 = D^w M_phi (Sec. 2.2)."""
+    return -0.5 * (b * _eye5(Ls) + c * ptilde(Ls, mf))
+
+
+def inverse5(M):
+    Ls = M.shape[0]
+    return np.linalg.inv(M.reshape(4 * Ls, 4 * Ls)).reshape(Ls, 4, Ls, 4)
+
+
+def adjoint5(M):
+    Ls = M.shape[0]
+    return np.conj(M.reshape(4 * Ls, 4 * Ls).T).reshape(Ls, 4, Ls, 4)
+
+
+def apply5(M, psi):
+    """(M psi)(s, x, alpha, a) = sum_{t, beta} M[s, alpha, t, beta] psi(t, x, beta, a)."""
+    Ls = M.shape[0]
+    lead = psi.shape[:-4]
+    vh = psi.shape[-3]
+    p = np.moveaxis(psi, -2, -3)                       # [..][Ls][4][V/2][3]
+    p = p.reshape(lead + (4 * Ls, vh * 3))
+    o = M.reshape(4 * Ls, 4 * Ls) @ p
+    o = o.reshape(lead + (Ls, 4, vh, 3))
+    return np.ascontiguousarray(np.moveaxis(o, -3, -2))
+
+
+# --------------------------------------------------------------------------
+# the Mobius domain-wall operator
+# --------------------------------------------------------------------------
+
+
+def norm2(a):
+    return float(np.vdot(a, a).real)
+
+
+@dataclass
+class MobiusDWF:
+    """Even-odd preconditioned Mobius operator on a gauge field.
+
+    Sec. 2.2: with M^4_{eo/oe} = D^w M_phi,
+      D    = 1 - M_5^-1 M^4_eo M_5^-1 M^4_oe                  (eq. dirac_equation)
+      A    = D^dag D                                           (eq. normal_equation)
+    """
+    U: np.ndarray
+    Ls: int
+    b: float
+    c: float
+    M5: float
+    mf: float
+
+    def __post_init__(self):
+        T, Z, Y, X = self.U.shape[:4]
+        self.dims = (X, Y, Z, T)
+        self.vh = X * Y * Z * T // 2
+        self.M5op = m5_matrix(self.Ls, self.b, self.c, self.M5, self.mf)
+        self.M5inv = inverse5(self.M5op)
+        self.Mphi = mphi_matrix(self.Ls, self.b, self.c, self.mf)
+        self.M5inv_dag = adjoint5(self.M5inv)
+        self.Mphi_dag = adjoint5(self.Mphi)
+
+    # M^4 restricted to one parity block: D^w M_phi
+    def m4(self, psi, out_parity):
+        return wilson_hop(self.U, apply5(self.Mphi, psi), out_parity)
+
+    def m4_dag(self, psi, out_parity):
+        """(M^4_{out,in})^dag = M_phi^dag (D^w)^dag, mapping parity 1-out -> out."""
+        return apply5(self.Mphi_dag, wilson_hop(self.U, psi, out_parity, dagger=True))
+
+    def D(self, psi_e):
+        """D psi_e = psi_e - M5^-1 M^4_eo M5^-1 M^4_oe psi_e."""
+        t = self.m4(psi_e, 1)
+        t = apply5(self.M5inv, t)
+        t = self.m4(t, 0)
+        t = apply5(self.M5inv, t)
+        return psi_e - t
+
+    def Ddag(self, chi_e):
+        """D^dag = 1 - (M^4_oe)^dag M5^-dag (M^4_eo)^dag M5^-dag."""
+        t = apply5(self.M5inv_dag, chi_e)
+        t = self.m4_dag(t, 1)          # (M^4_eo)^dag: even -> odd
+        t = apply5(self.M5inv_dag, t)
+        t = self.m4_dag(t, 0)          # (M^4_oe)^dag: odd -> even
+        return chi_e - t
+
+    def A(self, psi_e):
+        """A = D^dag D (Sec. 2.3, eq. DdagD)."""
+        return self.Ddag(self.D(psi_e))
+
+    # the unpreconditioned 5D operator on both parities (Sec. 2.2 block form)
+    def full(self, psi_e, psi_o):
+        """[[M_5, M^4_eo], [M^4_oe, M_5]] (psi_e, psi_o)."""
+        phi_e = apply5(self.M5op, psi_e) + self.m4(psi_o, 0)
+        phi_o = self.m4(psi_e, 1) + apply5(self.M5op, psi_o)
+        return phi_e, phi_o
+
+    def phi_hat(self, phi_e, phi_o):
+        """phi^_e = M5^-1 phi_e - M5^-1 M^4_eo M5^-1 phi_o (eq. dirac_equation)."""
+        t = apply5(self.M5inv, phi_o)
+        t = self.m4(t, 0)
+        return apply5(self.M5inv, phi_e) - apply5(self.M5inv, t)
+
+    def reconstruct_odd(self, psi_e, phi_o):
+        """psi_o = M5^-1 (phi_o - M^4_oe psi_e), the second block row."""
+        return apply5(self.M5inv, phi_o - self.m4(psi_e, 1))
+
+
+# --------------------------------------------------------------------------
+# subdomains and the local operator A_s (Sec. 2.3-2.4)
+# --------------------------------------------------------------------------
+
+
+def tiling_ok(dims, sub):
+    """Tilings on which A_s = R_s A R_s^T is what a zero pad of two sites
+    around the subdomain evaluates: even extents that divide the lattice, and
+    in every partitioned direction at least four sites outside the subdomain."""
+    for d, s in zip(dims, sub):
+        if d % 2 or s % 2 or s <= 0 or d % s:
+            return False
+        if s < d and d - s < 4:
+            return False
+    return True
+
+
+@dataclass
+class Tiling:
+    """Block decomposition of the even sites into subdomains (Sec. 2.1, 2.4)."""
+    dims: tuple
+    sub: tuple
+    index: list = field(init=False)
+
+    def __post_init__(self):
+        self.dims = tuple(int(d) for d in self.dims)
+        self.sub = tuple(int(s) for s in self.sub)
+        if not tiling_ok(self.dims, self.sub):
+            raise ValueError(f"tiling {self.sub} not valid on {self.dims}")
+        nb = [d // s for d, s in zip(self.dims, self.sub)]
+        c = parity_coords(self.dims, 0)
+        bx = [c[:, mu] // self.sub[mu] for mu in range(4)]
+        label = ((bx[3] * nb[2] + bx[2]) * nb[1] + bx[1]) * nb[0] + bx[0]
+        self.nsub = int(np.prod(nb))
+        self.label = label
+        self.index = [np.nonzero(label == k)[0] for k in range(self.nsub)]
+
+    def restrict(self, v):
+        """R_s v for every s: [nsub][Ls][n_s][4][3]."""
+        return np.stack([v[:, idx] for idx in self.index])
+
+    def embed(self, vs, vh):
+        """R_s^T v_s for every s, each into its own full even field."""
+        nsub, Ls = vs.shape[:2]
+        out = np.zeros((nsub, Ls, vh, 4, 3), dtype=np.complex128)
+        for k, idx in enumerate(self.index):
+            out[k][:, idx] = vs[k]
+        return out
+
+    def prolong(self, vs, vh):
+        """sum_s R_s^T v_s into one full even field."""
+        Ls = vs.shape[1]
+        out = np.zeros((Ls, vh, 4, 3), dtype=np.complex128)
+        for k, idx in enumerate(self.index):
+            out[:, idx] = vs[k]
+        return out
+
+
+def local_operator(op: MobiusDWF, tiling: Tiling, vs, subset=None, batch=8):
+    """A_s v_s = R_s A R_s^T v_s for each subdomain (Sec. 2.3, eq. diri: the
+    Dirichlet condition is imposed on the whole four-hop operator, so paths
+    that leave the subdomain and return -- the snake terms -- are kept).
+
+    Each v_s is embedded (zero elsewhere) into its own full even field, the
+    full A is applied, and the result is restricted back; ``batch`` fields go
+    through A together."""
+    ids = list(range(tiling.nsub)) if subset is None else list(subset)
+    out = np.empty_like(vs)
+    for j0 in range(0, len(ids), batch):
+        chunk = ids[j0:j0 + batch]
+        full = np.zeros((len(chunk), op.Ls, op.vh, 4, 3), dtype=np.complex128)
+        for j, k in enumerate(chunk):
+            full[j][:, tiling.index[k]] = vs[j0 + j]
+        Af = op.A(full)
+        for j, k in enumerate(chunk):
+            out[j0 + j] = Af[j][:, tiling.index[k]]
+    return out
+
+
+def inner_cg(op: MobiusDWF, tiling: Tiling, r, k, subset=None):
+    """Preconditioner z = (+)_s CG_k(A_s, r_s) (Sec. 2.4-2.5).
+
+    On every subdomain independently: z = 0, res = r_s, p = res,
+    rho = <res,res>; repeat k times: q = A_s p, alpha = rho/<p,q>,
+    z += alpha p, res -= alpha q, rho' = <res,res>, p = res + (rho'/rho) p.
+    No precision-based stop.  A subdomain whose rho or <p,q> is zero keeps
+    its current z.  Returns the restricted solutions [nsub][Ls][n_s][4][3]."""
+    ids = list(range(tiling.nsub)) if subset is None else list(subset)
+    rs = np.stack([r[:, tiling.index[j]] for j in ids])
+    z = np.zeros_like(rs)
+    res = rs.copy()
+    p = res.copy()
+    rho = np.array([norm2(res[j]) for j in range(len(ids))])
+    active = rho > 0.0
+    for _ in range(k):
+        q = local_operator(op, tiling, p, subset=ids)
+        for j in range(len(ids)):
+            if not active[j]:
+                continue
+            pq = np.vdot(p[j], q[j]).real
+            if pq == 0.0:
+                active[j] = False
+                continue
+            alpha = rho[j] / pq
+            z[j] += alpha * p[j]
+            res[j] -= alpha * q[j]
+            rho_new = norm2(res[j])
+            if rho_new == 0.0:
+                active[j] = False
+                continue
+            beta = rho_new / rho[j]
+            p[j] = res[j] + beta * p[j]
+            rho[j] = rho_new
+    return z
+
+
+def precondition(op, tiling, r, k):
+    """z = M^-1 r with M = (+)_s A_s approximated by k inner CG steps."""
+    zs = inner_cg(op, tiling, r, k)
+    return tiling.prolong(zs, op.vh)
+
+
+# --------------------------------------------------------------------------
+# outer solvers (Sec. 2.4, Alg. 1; Sec. 3.2 Polak-Ribiere beta)
+# --------------------------------------------------------------------------
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    converged: bool
+    history: list
+    true_rel_resid: float
+
+
+def pcg(op: MobiusDWF, b, tol, maxiter, precond=None, beta_rule="PR", x0=None,
+        callback=None):
+    """Preconditioned CG on A x = b (Alg. 1).
+
+    alpha = <r,z>/<p,Ap>, x += alpha p, r -= alpha Ap, z = M^-1 r,
+    beta = <z_new, r_new - r_old>/<z_old, r_old> (Polak-Ribiere) or
+    <z_new, r_new>/<z_old, r_old> (Fletcher-Reeves, as in Alg. 1), p = z + beta p.
+    Stops when ||r|| / ||b|| <= tol.  Without ``precond`` z = r (plain CG)."""
+    M = (lambda v: v) if precond is None else precond
+    bnorm = np.sqrt(norm2(b))
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - op.A(x) if x0 is not None else b.copy()
+    z = M(r)
+    p = z.copy()
+    rho = np.vdot(r, z).real
+    hist = [np.sqrt(norm2(r)) / bnorm]
+    converged = hist[-1] <= tol
+    it = 0
+    while not converged and it < maxiter:
+        q = op.A(p)
+        alpha = rho / np.vdot(p, q).real
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        it += 1
+        hist.append(np.sqrt(norm2(r)) / bnorm)
+        if callback is not None:
+            callback(it, x, r)
+        if hist[-1] <= tol:
+            converged = True
+            break
+        z = M(r)
+        rz = np.vdot(z, r).real
+        if beta_rule == "PR":
+            beta = (rz - np.vdot(z, r_old).real) / rho
+        else:
+            beta = rz / rho
+        rho = rz
+        p = z + beta * p
+    true = np.sqrt(norm2(b - op.A(x))) / bnorm
+    return x, SolveInfo(it, converged, hist, true)
+
+
+def mspcg(op, tiling, b, k, tol, maxiter, x0=None):
+    """MSPCG: Alg. 1 with the multi-splitting preconditioner and PR beta."""
+    return pcg(op, b, tol, maxiter, precond=lambda r: precondition(op, tiling, r, k),
+               beta_rule="PR", x0=x0)
+
+
+def cg(op, b, tol, maxiter, x0=None):
+    """Plain CG (Alg. 1 with M = 1, Fletcher-Reeves beta)."""
+    return pcg(op, b, tol, maxiter, precond=None, beta_rule="FR", x0=x0)
