@@ -1,0 +1,169 @@
+/*
+ * mspcg.h -- C ABI of the MI355X library for the multi-splitting
+ * preconditioned conjugate gradient (MSPCG) solve of the even-odd
+ * preconditioned Mobius domain-wall normal equations (arxiv 2104.05615).
+ *
+ * The library solves  D^dag D x = b  on the even checkerboard, with
+ *   D = 1 - M5^-1 M4_eo M5^-1 M4_oe,   M4 = D^w M_phi          (Sec. 2.2)
+ * by preconditioned CG (Alg. 1, Sec. 2.4) with Polak-Ribiere beta and
+ * reliable updates (Sec. 3.2), preconditioned by a fixed number of CG
+ * iterations on the local operator A_s of every subdomain, Dirichlet
+ * boundary on the whole four-hop operator so that snake terms are kept
+ * (Sec. 2.3-2.5).  Subdomains are virtual: they tile one GPU.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Every call returns an mspcg_status; 0 is success.  Nothing aborts or
+ *   throws across the ABI.  mspcg_last_error() gives a message for the last
+ *   non-OK status returned on the calling thread.
+ * - Host layouts (FP64, complex interleaved re, im):
+ *     gauge field   U[T][Z][Y][X][mu][3][3], mu = 0..3 for x, y, z, t;
+ *                   U[x][mu] is the SU(3) link from x to x + mu_hat.
+ *     5D field      psi[Ls][V/2][4][3] on the sites of one parity, ordered
+ *                   by lex/2 with lex = x + X*(y + Y*(z + Z*t)); spins in the
+ *                   chiral basis gamma_5 = diag(1, 1, -1, -1); P+ = spins 0,1.
+ *   Boundary conditions are periodic in all four directions.
+ * - Ownership: the handle owns every device copy and workspace it allocates.
+ *   The caller owns every buffer it passes in; the library never keeps a
+ *   caller pointer after a call returns.  Device pointers passed to the
+ *   *_device entry points are used in stream order on the given HIP stream
+ *   (NULL = the handle's own stream); the call returns after the work is
+ *   enqueued unless noted.
+ * - State: set_mobius, load_gauge and set_subdomains invalidate derived state
+ *   (tables, workspaces).  Calls that need state that is missing return
+ *   MSPCG_ERR_NO_GAUGE / MSPCG_ERR_NO_PARAMS / MSPCG_ERR_BAD_TILING.
+ * - A handle is not thread safe: one handle per thread or an external lock.
+ */
+#ifndef MSPCG_H
+#define MSPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mspcg_ctx* mspcg_t;
+
+typedef enum {
+  MSPCG_OK = 0,
+  MSPCG_NOT_CONVERGED = 1,     /* result and stats are filled in */
+  MSPCG_ERR_INVALID_ARG = -1,
+  MSPCG_ERR_BAD_TILING = -2,
+  MSPCG_ERR_NO_GAUGE = -3,
+  MSPCG_ERR_NO_PARAMS = -4,
+  MSPCG_ERR_OOM = -5,
+  MSPCG_ERR_HIP = -6,
+  MSPCG_ERR_BREAKDOWN = -7     /* NaN/Inf or a non-positive curvature in a reduction */
+} mspcg_status;
+
+typedef enum { MSPCG_FP64 = 0, MSPCG_FP32 = 1, MSPCG_FP16 = 2, MSPCG_BF16 = 3 } mspcg_prec;
+
+/* Operators exposed by mspcg_apply (each runs the same kernels the solver runs). */
+typedef enum {
+  MSPCG_OP_DSLASH_EO = 0,     /* D^w from odd to even sites (Sec. 2.2, def. of D^w)            */
+  MSPCG_OP_DSLASH_OE = 1,     /* D^w from even to odd sites                                     */
+  MSPCG_OP_DSLASH_DAG_EO = 2, /* (D^w)^dag from odd to even                                      */
+  MSPCG_OP_DSLASH_DAG_OE = 3, /* (D^w)^dag from even to odd                                      */
+  MSPCG_OP_M5 = 4,            /* M5 = (b(4-M5)+1) + (c(4-M5)-1) P~, diagonal in 4D              */
+  MSPCG_OP_M5INV = 5,         /* M5^-1                                                          */
+  MSPCG_OP_MPHI = 6,          /* M_phi = -(b + c P~)/2, so that M4 = D^w M_phi                  */
+  MSPCG_OP_D = 7,             /* D = 1 - M5^-1 M4_eo M5^-1 M4_oe (eq. dirac_equation), even      */
+  MSPCG_OP_DDAG = 8,          /* D^dag, even                                                     */
+  MSPCG_OP_A = 9,             /* A = D^dag D (eq. normal_equation), even                         */
+  MSPCG_OP_A_SUB = 10,        /* (+)_s A_s, A_s = R_s A R_s^T with snake terms (eq. diri), even   */
+  MSPCG_OP_PRECOND = 11       /* z = (+)_s CG_k(A_s, r_s), k = inner_iters (Sec. 2.4-2.5), even  */
+} mspcg_op;
+
+typedef struct {
+  double tol;             /* stop at ||b - A x|| / ||b|| <= tol (true residual, FP64)            */
+  int32_t maxiter;        /* outer iterations                                                     */
+  int32_t inner_iters;    /* k: fixed inner CG iterations per preconditioner application          */
+  mspcg_prec inner_prec;  /* storage of the inner CG: FP64, FP32, FP16 or BF16 (FP32 arithmetic)  */
+  mspcg_prec outer_prec;  /* outer PCG: FP64 or FP32 (FP32 uses FP64 reliable updates)            */
+  double reliable_delta;  /* reliable update when ||r|| < delta * max ||r|| since the last one     */
+  int32_t beta_rule;      /* 0 = Polak-Ribiere (Sec. 3.2), 1 = Fletcher-Reeves (Alg. 1)            */
+  int32_t use_precond;    /* 0 = plain CG (M = 1), 1 = MSPCG                                       */
+} mspcg_solver_params;
+
+typedef struct {
+  int32_t outer_iters;
+  int32_t inner_iters_total;
+  int32_t reliable_updates;
+  double true_rel_resid;  /* ||b - A x|| / ||b|| in FP64 at exit                                   */
+  double iter_rel_resid;  /* iterated residual at exit                                             */
+  double ms_total;        /* wall clock of the solve on the device stream                          */
+  double ms_precond;      /* part spent in the preconditioner (only when profiling is on)          */
+} mspcg_stats;
+
+/* Create a handle for an X*Y*Z*T lattice on HIP device `device`.  No HIP call
+ * is made here; the device is touched by the first call that needs it.
+ * Errors: INVALID_ARG if out is NULL, an extent is < 2 or odd, or device < 0. */
+mspcg_status mspcg_create(mspcg_t* out, const int32_t dims[4], int32_t device);
+
+/* Free the handle and everything it owns.  NULL is accepted. */
+mspcg_status mspcg_destroy(mspcg_t h);
+
+/* Copy the gauge field (host FP64, layout above; links SU(3), Sec. 2.2) to the
+ * device and convert it to the library's FP64 and FP32 link layouts.
+ * Errors: INVALID_ARG (NULL), HIP/OOM from the device. */
+mspcg_status mspcg_load_gauge(mspcg_t h, const double* U);
+
+/* Mobius parameters of M5 and M_phi (Sec. 2.2 with the Mobius construction the
+ * paper cites): fifth-dimension extent Ls >= 2, b, c, domain-wall height M5,
+ * quark mass mf.  Errors: INVALID_ARG for Ls < 2 or Ls > 32, or a singular M5. */
+mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double M5, double mf);
+
+/* Subdomain extents (X, Y, Z, T) of the virtual block decomposition used by the
+ * preconditioner (Sec. 2.1, 2.4).  Every extent must be even and divide the
+ * lattice extent, and in every partitioned direction (sub < lattice) the
+ * lattice must extend at least 4 sites past the subdomain, so that the zero
+ * pad of two sites (Sec. 3.1.2) evaluates R_s A R_s^T exactly.
+ * Errors: BAD_TILING otherwise. */
+mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]);
+
+/* Solver parameters (copied).  Errors: INVALID_ARG for tol <= 0, maxiter < 1,
+ * inner_iters < 0, outer_prec not FP64/FP32, an unknown precision or beta rule. */
+mspcg_status mspcg_set_solver(mspcg_t h, const mspcg_solver_params* p);
+
+/* Solve A x = b (A = D^dag D, eq. normal_equation) for one right-hand side.
+ * b, x: host FP64 even fields [Ls][V/2][4][3]; x0 (nullable) is the starting
+ * guess (r0 = b - A x0), else 0.  Synchronous.  st (nullable) gets the stats.
+ * Returns OK, NOT_CONVERGED (maxiter reached; x is the last iterate),
+ * BREAKDOWN (NaN/Inf), NO_GAUGE, NO_PARAMS, BAD_TILING (MSPCG without a tiling). */
+mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0, mspcg_stats* st);
+
+/* As mspcg_solve with device FP64 buffers b, x (layout above), x0 nullable.
+ * Runs on `hip_stream` (NULL = the handle's stream) and synchronizes it
+ * before returning (the convergence test reads the residual on the host). */
+mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const double* x0, void* hip_stream,
+                                mspcg_stats* st);
+
+/* Apply one operator (mspcg_op) in precision `prec` to a host FP64 field and
+ * return the result as host FP64: the input is converted to the storage of
+ * `prec`, the operator runs with that storage, the output is converted back.
+ * Synchronous.  Errors: INVALID_ARG (op/prec/NULL), NO_GAUGE, NO_PARAMS,
+ * BAD_TILING (A_SUB/PRECOND without a tiling). */
+mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out);
+
+/* As mspcg_apply with device FP64 buffers, stream ordered on hip_stream
+ * (NULL = the handle's stream); returns once the work is enqueued. */
+mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
+                                void* hip_stream);
+
+/* Kernel timing.  With profiling on, the library brackets every launch of its
+ * hop kernels with HIP events on the stream they run on; mspcg_get_kernel_time
+ * returns the number of timed launches and their summed duration in ms for a
+ * kernel class: 0 = outer FP32/FP64 hop kernels, 1 = subdomain (inner) hop
+ * kernels, 2 = preconditioner total.  Counters are reset by set_profiling(h, 1). */
+mspcg_status mspcg_set_profiling(mspcg_t h, int32_t on);
+mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, double* ms);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* mspcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSPCG_H */

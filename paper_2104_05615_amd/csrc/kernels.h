@@ -1,0 +1,126 @@
+// Host-side launch interface of the library's HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mspcg {
+
+enum class Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+
+// A single-parity 5D field in device memory, type-erased.
+struct FieldPtr {
+  void* data = nullptr;
+  float* scale = nullptr;
+  int64_t stride = 0;   // chunks per chunk-array (= n5)
+  Prec prec = Prec::F32;
+};
+
+template <typename S> inline Field<S> typed(const FieldPtr& f) {
+  Field<S> r;
+  r.data = reinterpret_cast<typename Field<S>::chunk*>(f.data);
+  r.scale = f.scale;
+  r.stride = f.stride;
+  return r;
+}
+
+// Fused epilogue after a hop, per 5D site (x, s) and chirality chi:
+//   y(s)   = E0 w(s) [or w(s) if w_identity] + E1 h(s) [or h(s) if E1 null]
+//   out(s) = E2 y(s) [or y(s) if E2 null]
+// with Ls x Ls real matrices per chirality ([2][Ls][Ls], calc precision).
+// If norm_partial is set, each block writes sum |y|^2 of its sites.
+struct Epilogue {
+  const void* E0 = nullptr;
+  const void* E1 = nullptr;
+  const void* E2 = nullptr;
+  bool w_identity = false;
+  double* norm_partial = nullptr;
+};
+
+struct HopGeometry {
+  Lattice lat;
+  int out_parity;
+  int Ls;
+};
+
+// slots of the outer solver's device scalar array
+enum ScalarSlot { SLOT_RHO = 0, SLOT_PAP, SLOT_ALPHA, SLOT_BETA, SLOT_RR, SLOT_RZ, SLOT_RZOLD, SLOT_R64, SLOT_TMP,
+                  SLOT_COUNT = 16 };
+enum FinishMode { FIN_STORE = 0, FIN_ALPHA, FIN_RHO, FIN_BETA_FR, FIN_BETA_PR };
+
+int sites_per_block(int Ls, Prec p);
+int64_t full_blocks(int64_t vh, int Ls, Prec p);
+
+// ---------------------------------------------------------------- site kernels
+void hop_full(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w,
+              const void* gauge, const HopGeometry& geo, bool dagger, const Epilogue& epi);
+void hop_sub(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, const void* gauge,
+             const Lattice& lat, int out_parity, const SubTables& tb, int nsub, int Ls, bool dagger,
+             const Epilogue& epi);
+// out = E w (E null: copy); optional |out|^2 partials (one per block)
+void apply5_full(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& w, const void* E, int64_t nsites,
+                 int Ls, double* norm_partial);
+// p <- z + beta p (beta = scal[beta_slot]);  out = E p
+void xpay_apply5(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& pvec, const FieldPtr& z,
+                 const double* scal, int beta_slot, const void* E, int64_t nsites, int Ls);
+
+// ---------------------------------------------------------------- layouts
+// canonical FP64 [Ls][nsites][4][3] complex <-> internal
+void pack_field(hipStream_t st, const FieldPtr& out, const double* canon, int64_t nsites, int Ls);
+void unpack_field(hipStream_t st, double* canon, const FieldPtr& in, int64_t nsites, int Ls);
+// gauge: canonical [T][Z][Y][X][4][3][3] complex FP64 -> [parity][mu][9][vh] double2 / float2
+void pack_gauge(hipStream_t st, void* out, bool fp64, const double* canon, const Lattice& lat);
+
+// ---------------------------------------------------------------- outer BLAS-1 (FP64 / FP32 fields)
+int64_t blas_blocks(int64_t nchunks);
+// x += alpha p ; rn = r - alpha q ; partial |rn|^2.  nreal = 24 * n5.
+void cg_update(hipStream_t st, Prec p, void* x, const void* pv, const void* r, const void* q, void* rn, int64_t nreal,
+               const double* scal, int alpha_slot, double* partial, int64_t nblocks);
+// partial Re<a,b1>, Re<a,b2> (b2 nullable)
+void dot2(hipStream_t st, Prec p, const void* a, const void* b1, const void* b2, int64_t nreal, double* partial1,
+          double* partial2, int64_t nblocks);
+// r64 = b - Ax ; partial |r64|^2 ; r_lo = (float) r64 if r_lo
+void residual64(hipStream_t st, const double* b, const double* Ax, double* r64, float* r_lo, int64_t n5,
+                double* partial, int64_t nblocks);
+// x64 += x_lo ; x_lo = 0
+void accum_lo(hipStream_t st, double* x64, float* xlo, int64_t n5);
+void f64_to_f32(hipStream_t st, const double* a, float* b, int64_t n5);
+// reduce partial sums (fixed order) and update solver scalars (FinishMode)
+void finish(hipStream_t st, const double* p1, const double* p2, int64_t n, double* scal, int mode, int slot);
+
+// ---------------------------------------------------------------- preconditioner (sub.hip)
+//
+// Per-subdomain inner CG state: rho[d], alpha[d], beta[d], active[d].
+struct SubScalars {
+  double* rho;
+  double* alpha;
+  double* beta;
+  int* active;
+};
+
+// Restrict the outer residual to the centre region of every subdomain:
+//   r_s = R_s r,  p_s = r_s,  t0 = E p_s (M_phi),  partial |r_s|^2 (per block, [d][bps])
+void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_outer, const FieldPtr& rs,
+                  const FieldPtr& ps, const FieldPtr& t0, const void* E, const Lattice& lat, const SubTables& tc,
+                  int nsub, int Ls, double* partial);
+// z_s (+)= alpha_d p_s ; r_s -= alpha_d q_s ; partial |r_s|^2  (first: z_s = alpha_d p_s)
+void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
+                const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
+                double* partial);
+// p_s = r_s + beta_d p_s ; t0 = E p_s
+void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0,
+               const SubScalars& sc, const void* E, const SubTables& tc, int nsub, int Ls);
+// z = sum_s R_s^T z_s (outer precision); partials Re<z, r>, Re<z, r_old> (r_old nullable)
+void sub_prolong(hipStream_t st, Prec outer, Prec inner, const FieldPtr& z_outer, const FieldPtr& zs,
+                 const FieldPtr& r_outer, const FieldPtr* rold_outer, const Lattice& lat, const SubTables& tc,
+                 int nsub, int Ls, double* partial1, double* partial2);
+// per-subdomain scalar updates from [d][bps] partials:
+//   SUB_INIT : rho = S, active = rho > 0
+//   SUB_ALPHA: alpha = rho / S (0 and inactive if S <= 0 or not finite)
+//   SUB_BETA : if S == 0 inactive; beta = S / rho; rho = S
+enum SubFinish { SUB_INIT = 0, SUB_ALPHA, SUB_BETA };
+void sub_finish(hipStream_t st, const double* partial, int bps, int nsub, const SubScalars& sc, int mode);
+
+}  // namespace mspcg

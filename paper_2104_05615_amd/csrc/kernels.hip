@@ -1,0 +1,489 @@
+// Full-lattice kernels: the hop operator with its fused epilogue, the
+// fifth-dimension-only operator, layout conversions, the outer solver's
+// BLAS-1 and deterministic reductions.
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+#include "sitekern.h"
+
+namespace mspcg {
+
+#define LAUNCH_CHECK()                                                                \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("kernel launch: ") +   \
+                                                   hipGetErrorString(e_));            \
+  } while (0)
+
+int sites_per_block(int Ls, Prec p) {
+  // blocks of <= 256 threads; FP64 tiles kept small for occupancy
+  int ns = 256 / Ls;
+  if (p == Prec::F64 && ns > 8) ns = 8;
+  if (ns < 1) ns = 1;
+  return ns;
+}
+
+int64_t full_blocks(int64_t vh, int Ls, Prec p) {
+  const int ns = sites_per_block(Ls, p);
+  return (vh + ns - 1) / ns;
+}
+
+// ---------------------------------------------------------------- hop launch
+
+template <typename Geo, typename S>
+static void launch_hop(hipStream_t st, const Geo& geo, int64_t nblocks, const FieldPtr& out, const FieldPtr& in,
+                       const FieldPtr* w, int Ls, int ns, bool dagger, const Epilogue& epi) {
+  using T = calc_t<S>;
+  const size_t lds = site_lds_bytes<T>(ns, Ls, w != nullptr && !epi.w_identity);
+  Field<S> wf = w ? typed<S>(*w) : Field<S>{};
+  const T* E0 = (const T*)epi.E0;
+  const T* E1 = (const T*)epi.E1;
+  const T* E2 = (const T*)epi.E2;
+  dim3 grid((unsigned)nblocks), block(site_block_threads(ns, Ls));
+  const int wid = epi.w_identity ? 1 : 0;
+  if (dagger) {
+    if (w) hipLaunchKernelGGL((k_hop<Geo, S, true, true>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
+                              Ls, ns, E0, E1, E2, wid, epi.norm_partial);
+    else hipLaunchKernelGGL((k_hop<Geo, S, true, false>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
+                            Ls, ns, E0, E1, E2, wid, epi.norm_partial);
+  } else {
+    if (w) hipLaunchKernelGGL((k_hop<Geo, S, false, true>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
+                              Ls, ns, E0, E1, E2, wid, epi.norm_partial);
+    else hipLaunchKernelGGL((k_hop<Geo, S, false, false>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
+                            Ls, ns, E0, E1, E2, wid, epi.norm_partial);
+  }
+  LAUNCH_CHECK();
+}
+
+template <typename S>
+static void hop_full_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, const void* gauge,
+                       const HopGeometry& geo, bool dagger, const Epilogue& epi) {
+  using T = calc_t<S>;
+  FullGeo<T> g;
+  g.lat = geo.lat;
+  g.par = geo.out_parity;
+  g.g.data = reinterpret_cast<const typename Gauge<T>::c2*>(gauge);
+  g.g.vh = geo.lat.vh;
+  const int ns = sites_per_block(geo.Ls, out.prec);
+  launch_hop<FullGeo<T>, S>(st, g, (geo.lat.vh + ns - 1) / ns, out, in, w, geo.Ls, ns, dagger, epi);
+}
+
+void hop_full(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w,
+              const void* gauge, const HopGeometry& geo, bool dagger, const Epilogue& epi) {
+  switch (p) {
+    case Prec::F64: hop_full_t<double>(st, out, in, w, gauge, geo, dagger, epi); break;
+    case Prec::F32: hop_full_t<float>(st, out, in, w, gauge, geo, dagger, epi); break;
+    case Prec::F16: hop_full_t<__half>(st, out, in, w, gauge, geo, dagger, epi); break;
+    case Prec::BF16: hop_full_t<__hip_bfloat16>(st, out, in, w, gauge, geo, dagger, epi); break;
+  }
+}
+
+template <typename S>
+static void hop_sub_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, const void* gauge,
+                      const Lattice& lat, int out_parity, const SubTables& tb, int nsub, int Ls, bool dagger,
+                      const Epilogue& epi) {
+  using T = calc_t<S>;
+  SubGeo<T> g;
+  g.tb = tb;
+  g.lat = lat;
+  g.par = out_parity;
+  g.g.data = reinterpret_cast<const typename Gauge<T>::c2*>(gauge);
+  g.g.vh = lat.vh;
+  const int ns = sites_per_block(Ls, out.prec);
+  launch_hop<SubGeo<T>, S>(st, g, (int64_t)nsub * tb.bps, out, in, w, Ls, ns, dagger, epi);
+}
+
+void hop_sub(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, const void* gauge,
+             const Lattice& lat, int out_parity, const SubTables& tb, int nsub, int Ls, bool dagger,
+             const Epilogue& epi) {
+  switch (p) {
+    case Prec::F64: hop_sub_t<double>(st, out, in, w, gauge, lat, out_parity, tb, nsub, Ls, dagger, epi); break;
+    case Prec::F32: hop_sub_t<float>(st, out, in, w, gauge, lat, out_parity, tb, nsub, Ls, dagger, epi); break;
+    case Prec::F16: hop_sub_t<__half>(st, out, in, w, gauge, lat, out_parity, tb, nsub, Ls, dagger, epi); break;
+    case Prec::BF16:
+      hop_sub_t<__hip_bfloat16>(st, out, in, w, gauge, lat, out_parity, tb, nsub, Ls, dagger, epi);
+      break;
+  }
+}
+
+// ---------------------------------------------------------------- 5D-only ops
+
+// out = E w (copy when E is null); optional |out|^2 partial per block.
+// With beta_slot >= 0 the input is first updated in place,
+//   w <- z + beta w  (beta = scal[beta_slot]),
+// which is the search-direction update of CG fused with the M_phi that
+// starts the next operator application.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_apply5(Field<S> out, Field<S> w, Field<S> z, const double* scal, int beta_slot, int64_t nsites, int Ls, int ns,
+         const calc_t<S>* E, double* norm_partial) {
+  using T = calc_t<S>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* red = reinterpret_cast<double*>(lds_raw);
+  T* mats = reinterpret_cast<T*>(red + 16);
+  T* tileA = mats + 2 * Ls * Ls;
+  const int tid = threadIdx.x;
+  const bool inb = tid < ns * Ls;
+  const int sl = inb ? tid / Ls : 0, s = inb ? tid - sl * Ls : 0;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t site = blk * ns + sl;
+  const bool valid = inb && site < nsites;
+  const int64_t i5 = site * Ls + s;
+  if (E)
+    for (int k = tid; k < 2 * Ls * Ls; k += blockDim.x) mats[k] = E[k];
+  T v[24];
+  if (valid) {
+    load_site(w, i5, v);
+    if (beta_slot >= 0) {
+      const T beta = (T)scal[beta_slot];
+      T zv[24];
+      load_site(z, i5, zv);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) v[k] = zv[k] + beta * v[k];
+      store_site(w, i5, v);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = 0;
+  }
+  T* my = tileA + sl * tile_stride(Ls);
+  if (inb) tile_put(my, s, v);
+  __syncthreads();
+  if (E && inb) mat5_lds(my, mats, s, Ls, v, false);
+  if (norm_partial) {
+    double loc = 0;
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < 24; ++k) loc += (double)v[k] * (double)v[k];
+    }
+    const double tot = block_sum(loc, red);
+    if (tid == 0) norm_partial[blk] = tot;
+  }
+  if (valid) store_site(out, i5, v);
+}
+
+template <typename S>
+static void apply5_t(hipStream_t st, const FieldPtr& out, const FieldPtr& w, const FieldPtr* z, const double* scal,
+                     int beta_slot, const void* E, int64_t nsites, int Ls, double* norm_partial) {
+  using T = calc_t<S>;
+  const int ns = sites_per_block(Ls, out.prec);
+  const int64_t nb = (nsites + ns - 1) / ns;
+  const size_t lds = 16 * sizeof(double) + sizeof(T) * (size_t)(2 * Ls * Ls + ns * tile_stride(Ls));
+  Field<S> zf = z ? typed<S>(*z) : Field<S>{};
+  hipLaunchKernelGGL((k_apply5<S>), dim3((unsigned)nb), dim3(site_block_threads(ns, Ls)), lds, st, typed<S>(out), typed<S>(w), zf, scal,
+                     beta_slot, nsites, Ls, ns, (const T*)E, norm_partial);
+  LAUNCH_CHECK();
+}
+
+void apply5_full(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& w, const void* E, int64_t nsites,
+                 int Ls, double* norm_partial) {
+  switch (p) {
+    case Prec::F64: apply5_t<double>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial); break;
+    case Prec::F32: apply5_t<float>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial); break;
+    case Prec::F16: apply5_t<__half>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial); break;
+    case Prec::BF16: apply5_t<__hip_bfloat16>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial); break;
+  }
+}
+
+void xpay_apply5(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& pvec, const FieldPtr& z,
+                 const double* scal, int beta_slot, const void* E, int64_t nsites, int Ls) {
+  switch (p) {
+    case Prec::F64: apply5_t<double>(st, out, pvec, &z, scal, beta_slot, E, nsites, Ls, nullptr); break;
+    case Prec::F32: apply5_t<float>(st, out, pvec, &z, scal, beta_slot, E, nsites, Ls, nullptr); break;
+    default: throw std::runtime_error("xpay_apply5: outer vectors are FP64 or FP32");
+  }
+}
+
+// ---------------------------------------------------------------- layout conversion
+
+template <typename S>
+__global__ void k_pack(Field<S> out, const double* canon, int64_t nsites, int Ls) {
+  const int64_t i5 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i5 >= nsites * Ls) return;
+  const int64_t site = i5 / Ls;
+  const int s = (int)(i5 - site * Ls);
+  const double* src = canon + ((int64_t)s * nsites + site) * 24;
+  double v[24];
+#pragma unroll
+  for (int k = 0; k < 24; ++k) v[k] = src[k];
+  store_site(out, i5, v);
+}
+
+template <typename S>
+__global__ void k_unpack(double* canon, Field<S> in, int64_t nsites, int Ls) {
+  const int64_t i5 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i5 >= nsites * Ls) return;
+  const int64_t site = i5 / Ls;
+  const int s = (int)(i5 - site * Ls);
+  double v[24];
+  load_site(in, i5, v);
+  double* dst = canon + ((int64_t)s * nsites + site) * 24;
+#pragma unroll
+  for (int k = 0; k < 24; ++k) dst[k] = v[k];
+}
+
+void pack_field(hipStream_t st, const FieldPtr& out, const double* canon, int64_t nsites, int Ls) {
+  const int64_t n = nsites * Ls;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (out.prec) {
+    case Prec::F64: hipLaunchKernelGGL(k_pack<double>, grid, block, 0, st, typed<double>(out), canon, nsites, Ls); break;
+    case Prec::F32: hipLaunchKernelGGL(k_pack<float>, grid, block, 0, st, typed<float>(out), canon, nsites, Ls); break;
+    case Prec::F16: hipLaunchKernelGGL(k_pack<__half>, grid, block, 0, st, typed<__half>(out), canon, nsites, Ls); break;
+    case Prec::BF16:
+      hipLaunchKernelGGL(k_pack<__hip_bfloat16>, grid, block, 0, st, typed<__hip_bfloat16>(out), canon, nsites, Ls);
+      break;
+  }
+  LAUNCH_CHECK();
+}
+
+void unpack_field(hipStream_t st, double* canon, const FieldPtr& in, int64_t nsites, int Ls) {
+  const int64_t n = nsites * Ls;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (in.prec) {
+    case Prec::F64: hipLaunchKernelGGL(k_unpack<double>, grid, block, 0, st, canon, typed<double>(in), nsites, Ls); break;
+    case Prec::F32: hipLaunchKernelGGL(k_unpack<float>, grid, block, 0, st, canon, typed<float>(in), nsites, Ls); break;
+    case Prec::F16: hipLaunchKernelGGL(k_unpack<__half>, grid, block, 0, st, canon, typed<__half>(in), nsites, Ls); break;
+    case Prec::BF16:
+      hipLaunchKernelGGL(k_unpack<__hip_bfloat16>, grid, block, 0, st, canon, typed<__hip_bfloat16>(in), nsites, Ls);
+      break;
+  }
+  LAUNCH_CHECK();
+}
+
+template <typename C2>
+__global__ void k_pack_gauge(C2* out, const double* canon, Lattice lat) {
+  const int64_t lex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t V = 2 * lat.vh;
+  if (lex >= V) return;
+  const int x = (int)(lex % lat.X);
+  const int64_t r = lex / lat.X;
+  const int y = (int)(r % lat.Y);
+  const int64_t r2 = r / lat.Y;
+  const int z = (int)(r2 % lat.Z);
+  const int t = (int)(r2 / lat.Z);
+  const int par = (x + y + z + t) & 1;
+  const int64_t cb = lex >> 1;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int k = 0; k < 9; ++k) {
+      const double* src = canon + ((lex * 4 + mu) * 9 + k) * 2;
+      C2 c;
+      c.x = src[0];
+      c.y = src[1];
+      out[((int64_t)(par * 4 + mu) * 9 + k) * lat.vh + cb] = c;
+    }
+}
+
+void pack_gauge(hipStream_t st, void* out, bool fp64, const double* canon, const Lattice& lat) {
+  const int64_t V = 2 * lat.vh;
+  dim3 grid((unsigned)((V + 255) / 256)), block(256);
+  if (fp64) hipLaunchKernelGGL(k_pack_gauge<double2>, grid, block, 0, st, (double2*)out, canon, lat);
+  else hipLaunchKernelGGL(k_pack_gauge<float2>, grid, block, 0, st, (float2*)out, canon, lat);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- outer BLAS-1
+//
+// Outer vectors (FP64 or FP32) are flat arrays of chunks; every kernel runs
+// a fixed grid so its per-block partial sums land in a fixed order.
+
+int64_t blas_blocks(int64_t nchunks) {
+  int64_t nb = (nchunks + 255) / 256;
+  return nb > 2048 ? 2048 : (nb < 1 ? 1 : nb);
+}
+
+template <typename C> struct ChunkOps;
+template <> struct ChunkOps<float4> {
+  static constexpr int n = 4;
+  __device__ static float get(const float4& c, int k) { return k == 0 ? c.x : k == 1 ? c.y : k == 2 ? c.z : c.w; }
+  __device__ static void set(float4& c, int k, float v) {
+    if (k == 0) c.x = v; else if (k == 1) c.y = v; else if (k == 2) c.z = v; else c.w = v;
+  }
+};
+template <> struct ChunkOps<double2> {
+  static constexpr int n = 2;
+  __device__ static double get(const double2& c, int k) { return k == 0 ? c.x : c.y; }
+  __device__ static void set(double2& c, int k, double v) { if (k == 0) c.x = v; else c.y = v; }
+};
+
+// x += alpha p ; rn = r - alpha q ; partial |rn|^2     (alpha = scal[alpha_slot])
+template <typename C>
+__global__ void __launch_bounds__(256)
+k_cg_update(C* x, const C* p, const C* r, const C* q, C* rn, int64_t n, const double* scal, int alpha_slot,
+            double* partial) {
+  __shared__ double red[16];
+  using O = ChunkOps<C>;
+  const double alpha = scal[alpha_slot];
+  double loc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    C xv = x[i], pv = p[i], rv = r[i], qv = q[i], ov;
+#pragma unroll
+    for (int k = 0; k < O::n; ++k) {
+      O::set(xv, k, O::get(xv, k) + alpha * O::get(pv, k));
+      const double v = O::get(rv, k) - alpha * O::get(qv, k);
+      O::set(ov, k, v);
+      const double vs = O::get(ov, k);
+      loc += vs * vs;
+    }
+    x[i] = xv;
+    rn[i] = ov;
+  }
+  const double tot = block_sum(loc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// partial Re<a, b1>, Re<a, b2> (b2 nullable)
+template <typename C>
+__global__ void __launch_bounds__(256)
+k_dot2(const C* a, const C* b1, const C* b2, int64_t n, double* partial1, double* partial2) {
+  __shared__ double red[16];
+  using O = ChunkOps<C>;
+  double l1 = 0, l2 = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const C av = a[i], bv = b1[i];
+#pragma unroll
+    for (int k = 0; k < O::n; ++k) l1 += (double)O::get(av, k) * (double)O::get(bv, k);
+    if (b2) {
+      const C cv = b2[i];
+#pragma unroll
+      for (int k = 0; k < O::n; ++k) l2 += (double)O::get(av, k) * (double)O::get(cv, k);
+    }
+  }
+  double t1 = block_sum(l1, red);
+  if (threadIdx.x == 0) partial1[blockIdx.x] = t1;
+  if (b2) {
+    double t2 = block_sum(l2, red);
+    if (threadIdx.x == 0) partial2[blockIdx.x] = t2;
+  }
+}
+
+// Mixed-precision helpers.  An FP32 chunk j of 5D site i holds complex
+// numbers 2j and 2j+1 of that site; in FP64 they are chunks 2j and 2j+1.
+// Both layouts use stride n5 (chunks per chunk-array).
+
+// reliable update residual: r64 = b - Ax ; partial |r64|^2 ; r_lo = (float) r64 when given
+__global__ void __launch_bounds__(256)
+k_residual64(const double2* b, const double2* Ax, double2* r64, float4* r_lo, int64_t n5, double* partial) {
+  __shared__ double red[16];
+  double loc = 0;
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < 6 * n5; f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = f / n5, i = f - j * n5;
+    const int64_t ia = 2 * j * n5 + i, ib = ia + n5;
+    const double2 b0 = b[ia], b1 = b[ib], a0 = Ax[ia], a1 = Ax[ib];
+    const double2 o0 = make_double2(b0.x - a0.x, b0.y - a0.y), o1 = make_double2(b1.x - a1.x, b1.y - a1.y);
+    r64[ia] = o0;
+    r64[ib] = o1;
+    loc += o0.x * o0.x + o0.y * o0.y + o1.x * o1.x + o1.y * o1.y;
+    if (r_lo) r_lo[f] = make_float4((float)o0.x, (float)o0.y, (float)o1.x, (float)o1.y);
+  }
+  const double tot = block_sum(loc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// x64 += x_lo ; x_lo = 0
+__global__ void k_accum_lo(double2* x64, float4* xlo, int64_t n5) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < 6 * n5; f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = f / n5, i = f - j * n5;
+    const int64_t ia = 2 * j * n5 + i, ib = ia + n5;
+    const float4 v = xlo[f];
+    double2 a = x64[ia], c = x64[ib];
+    a.x += v.x; a.y += v.y; c.x += v.z; c.y += v.w;
+    x64[ia] = a;
+    x64[ib] = c;
+    xlo[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+// FP64 field -> FP32 field
+__global__ void k_f64_to_f32(const double2* a, float4* o, int64_t n5) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < 6 * n5; f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = f / n5, i = f - j * n5;
+    const double2 u = a[2 * j * n5 + i], v = a[(2 * j + 1) * n5 + i];
+    o[f] = make_float4((float)u.x, (float)u.y, (float)v.x, (float)v.y);
+  }
+}
+
+void cg_update(hipStream_t st, Prec p, void* x, const void* pv, const void* r, const void* q, void* rn, int64_t nreal,
+               const double* scal, int alpha_slot, double* partial, int64_t nblocks) {
+  if (p == Prec::F32)
+    hipLaunchKernelGGL(k_cg_update<float4>, dim3((unsigned)nblocks), dim3(256), 0, st, (float4*)x,
+                       (const float4*)pv, (const float4*)r, (const float4*)q, (float4*)rn, nreal / 4, scal, alpha_slot,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_cg_update<double2>, dim3((unsigned)nblocks), dim3(256), 0, st, (double2*)x,
+                       (const double2*)pv, (const double2*)r, (const double2*)q, (double2*)rn, nreal / 2, scal,
+                       alpha_slot, partial);
+  LAUNCH_CHECK();
+}
+
+void dot2(hipStream_t st, Prec p, const void* a, const void* b1, const void* b2, int64_t nreal, double* partial1,
+          double* partial2, int64_t nblocks) {
+  if (p == Prec::F32)
+    hipLaunchKernelGGL(k_dot2<float4>, dim3((unsigned)nblocks), dim3(256), 0, st, (const float4*)a,
+                       (const float4*)b1, (const float4*)b2, nreal / 4, partial1, partial2);
+  else
+    hipLaunchKernelGGL(k_dot2<double2>, dim3((unsigned)nblocks), dim3(256), 0, st, (const double2*)a,
+                       (const double2*)b1, (const double2*)b2, nreal / 2, partial1, partial2);
+  LAUNCH_CHECK();
+}
+
+void residual64(hipStream_t st, const double* b, const double* Ax, double* r64, float* r_lo, int64_t n5,
+                double* partial, int64_t nblocks) {
+  hipLaunchKernelGGL(k_residual64, dim3((unsigned)nblocks), dim3(256), 0, st, (const double2*)b, (const double2*)Ax,
+                     (double2*)r64, (float4*)r_lo, n5, partial);
+  LAUNCH_CHECK();
+}
+
+void accum_lo(hipStream_t st, double* x64, float* xlo, int64_t n5) {
+  hipLaunchKernelGGL(k_accum_lo, dim3(2048), dim3(256), 0, st, (double2*)x64, (float4*)xlo, n5);
+  LAUNCH_CHECK();
+}
+
+void f64_to_f32(hipStream_t st, const double* a, float* b, int64_t n5) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(2048), dim3(256), 0, st, (const double2*)a, (float4*)b, n5);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- scalars
+//
+// k_finish reduces one or two partial arrays in a fixed order and updates the
+// solver scalars in `scal` (slots in kernels.h):
+//   FIN_STORE : scal[slot] = S1
+//   FIN_ALPHA : scal[PAP] = S1, alpha = rho / pAp
+//   FIN_RHO   : scal[RHO] = S1
+//   FIN_BETA_FR: rz = S1, beta = rz / rho, rho = rz
+//   FIN_BETA_PR: rz = S1, rzold = S2, beta = (rz - rzold) / rho, rho = rz
+__global__ void k_finish(const double* p1, const double* p2, int64_t n, double* scal, int mode, int slot) {
+  __shared__ double red[16];
+  double v1 = 0, v2 = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    v1 += p1[i];
+    if (p2) v2 += p2[i];
+  }
+  const double s1 = block_sum(v1, red);
+  const double s2 = p2 ? block_sum(v2, red) : 0.0;
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case FIN_STORE: scal[slot] = s1; break;
+    case FIN_ALPHA: scal[SLOT_PAP] = s1; scal[SLOT_ALPHA] = scal[SLOT_RHO] / s1; break;
+    case FIN_RHO: scal[SLOT_RHO] = s1; break;
+    case FIN_BETA_FR:
+      scal[SLOT_RZ] = s1;
+      scal[SLOT_BETA] = s1 / scal[SLOT_RHO];
+      scal[SLOT_RHO] = s1;
+      break;
+    case FIN_BETA_PR:
+      scal[SLOT_RZ] = s1;
+      scal[SLOT_RZOLD] = s2;
+      scal[SLOT_BETA] = (s1 - s2) / scal[SLOT_RHO];
+      scal[SLOT_RHO] = s1;
+      break;
+  }
+}
+
+void finish(hipStream_t st, const double* p1, const double* p2, int64_t n, double* scal, int mode, int slot) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, p1, p2, n, scal, mode, slot);
+  LAUNCH_CHECK();
+}
+
+}  // namespace mspcg

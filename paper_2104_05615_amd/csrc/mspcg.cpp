@@ -1,0 +1,988 @@
+// Host side of the library: the handle, the fifth-dimension matrices, the
+// subdomain region tables, the operator chains, the outer solver and the
+// C ABI declared in include/mspcg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "mspcg.h"
+
+using namespace mspcg;
+
+// ==========================================================================
+// errors
+// ==========================================================================
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+  mspcg_status code;
+  Error(mspcg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess) {                                                                         \
+      throw Error(e_ == hipErrorOutOfMemory ? MSPCG_ERR_OOM : MSPCG_ERR_HIP,                        \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                                  \
+    }                                                                                               \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  void ensure(size_t bytes) {
+    if (bytes <= n && p) return;
+    release();
+    HIPCHK(hipMalloc(&p, bytes ? bytes : 16));
+    n = bytes;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+Prec to_prec(mspcg_prec p) {
+  switch (p) {
+    case MSPCG_FP64: return Prec::F64;
+    case MSPCG_FP32: return Prec::F32;
+    case MSPCG_FP16: return Prec::F16;
+    case MSPCG_BF16: return Prec::BF16;
+  }
+  throw Error(MSPCG_ERR_INVALID_ARG, "unknown precision");
+}
+
+size_t chunk_bytes(Prec p) { return p == Prec::F64 ? 192 : p == Prec::F32 ? 96 : 48; }
+
+// --------------------------------------------------------------------------
+// fifth-dimension matrices, per chirality (0: P+, 1: P-), Ls x Ls, real.
+// P~ on P+ shifts s -> s+1 with psi(-1) = -mf psi(Ls-1); on P- it is the
+// transpose.  M5 = a0 + a1 P~, M_phi = -(b + c P~)/2 (Sec. 2.2 with the
+// Mobius construction).  M5^-1 from the geometric series of (a0 + a1 S)^-1
+// with S^Ls = -mf.
+// --------------------------------------------------------------------------
+enum MatId {
+  MAT_MPHI = 0,     // M_phi
+  MAT_Q,            // M_phi M5^-1
+  MAT_NEG_M5INV,    // -M5^-1
+  MAT_M5INV_T,      // M5^-dag
+  MAT_QT,           // (M_phi M5^-1)^dag
+  MAT_M5_T,         // M5^dag
+  MAT_NEG_MPHI_T,   // -M_phi^dag
+  MAT_M5,
+  MAT_M5INV,
+  MAT_COUNT
+};
+
+struct Mats {
+  int Ls;
+  std::vector<double> m;  // [MAT_COUNT][2][Ls][Ls]
+  double* at(int id, int chi) { return m.data() + ((size_t)id * 2 + chi) * Ls * Ls; }
+};
+
+Mats build_mats(int Ls, double b, double c, double M5, double mf) {
+  Mats M;
+  M.Ls = Ls;
+  M.m.assign((size_t)MAT_COUNT * 2 * Ls * Ls, 0.0);
+  const double a0 = b * (4.0 - M5) + 1.0, a1 = c * (4.0 - M5) - 1.0;
+  if (a0 == 0.0) throw Error(MSPCG_ERR_INVALID_ARG, "M5 operator singular: b(4-M5)+1 = 0");
+  const double kap = -a1 / a0;
+  const double den = a0 * (1.0 + mf * std::pow(kap, Ls));
+  if (den == 0.0 || !std::isfinite(den)) throw Error(MSPCG_ERR_INVALID_ARG, "M5 operator singular");
+  std::vector<double> S(Ls * Ls, 0.0), Minv(Ls * Ls), Mp(Ls * Ls), M5m(Ls * Ls), Q(Ls * Ls);
+  for (int s = 1; s < Ls; ++s) S[s * Ls + s - 1] = 1.0;
+  S[0 * Ls + Ls - 1] = -mf;
+  for (int s = 0; s < Ls; ++s)
+    for (int t = 0; t < Ls; ++t) {
+      Minv[s * Ls + t] = s >= t ? std::pow(kap, s - t) / den : -mf * std::pow(kap, s - t + Ls) / den;
+      const double id = s == t ? 1.0 : 0.0;
+      Mp[s * Ls + t] = -0.5 * (b * id + c * S[s * Ls + t]);
+      M5m[s * Ls + t] = a0 * id + a1 * S[s * Ls + t];
+    }
+  for (int s = 0; s < Ls; ++s)
+    for (int t = 0; t < Ls; ++t) {
+      double acc = 0;
+      for (int u = 0; u < Ls; ++u) acc += Mp[s * Ls + u] * Minv[u * Ls + t];
+      Q[s * Ls + t] = acc;
+    }
+  // chirality 0 uses the matrices as built; chirality 1 their transposes
+  auto put = [&](int id, const std::vector<double>& A, double sign, bool dag) {
+    for (int chi = 0; chi < 2; ++chi) {
+      double* o = M.at(id, chi);
+      const bool tr = (chi == 1) != dag;
+      for (int s = 0; s < Ls; ++s)
+        for (int t = 0; t < Ls; ++t) o[s * Ls + t] = sign * (tr ? A[t * Ls + s] : A[s * Ls + t]);
+    }
+  };
+  put(MAT_MPHI, Mp, 1.0, false);
+  put(MAT_Q, Q, 1.0, false);
+  put(MAT_NEG_M5INV, Minv, -1.0, false);
+  put(MAT_M5INV_T, Minv, 1.0, true);
+  put(MAT_QT, Q, 1.0, true);
+  put(MAT_M5_T, M5m, 1.0, true);
+  put(MAT_NEG_MPHI_T, Mp, -1.0, true);
+  put(MAT_M5, M5m, 1.0, false);
+  put(MAT_M5INV, Minv, 1.0, false);
+  return M;
+}
+
+// --------------------------------------------------------------------------
+// subdomain regions (shared by all subdomains, which are translates)
+// --------------------------------------------------------------------------
+struct Region {
+  std::vector<short4> coords;
+  std::vector<int> index;   // box index -> region index or -1
+};
+
+struct HostTables {
+  Region C, N1, N2;                                    // C even, N1 odd, N2 even
+  std::vector<int> nbr1, nbr2, nbr3, nbr4;             // h1: N1<-C, h2: N2<-N1, h3: N1<-N2, h4: C<-N1
+  std::vector<int> wmap2, wmap4;                       // N2 -> C, C -> N2
+};
+
+bool tiling_valid(const int* dims, const int* sub, std::string& why) {
+  for (int m = 0; m < 4; ++m) {
+    if (sub[m] <= 0 || sub[m] % 2 || dims[m] % sub[m]) {
+      why = "subdomain extents must be even and divide the lattice";
+      return false;
+    }
+    if (sub[m] < dims[m] && dims[m] - sub[m] < 4) {
+      why = "a partitioned direction needs at least 4 sites outside the subdomain";
+      return false;
+    }
+  }
+  return true;
+}
+
+HostTables build_tables(const int* dims, const int* sub) {
+  bool part[4];
+  int lo[4], ext[4];
+  for (int m = 0; m < 4; ++m) {
+    part[m] = sub[m] < dims[m];
+    lo[m] = part[m] ? -2 : 0;
+    ext[m] = part[m] ? sub[m] + 4 : dims[m];
+  }
+  const int64_t box = (int64_t)ext[0] * ext[1] * ext[2] * ext[3];
+  auto box_index = [&](const int* l) {
+    return ((int64_t)(l[3] - lo[3]) * ext[2] + (l[2] - lo[2])) * ext[1] * ext[0] + (int64_t)(l[1] - lo[1]) * ext[0] +
+           (l[0] - lo[0]);
+  };
+  HostTables H;
+  H.C.index.assign(box, -1);
+  H.N1.index.assign(box, -1);
+  H.N2.index.assign(box, -1);
+  int l[4];
+  for (l[3] = lo[3]; l[3] < lo[3] + ext[3]; ++l[3])
+    for (l[2] = lo[2]; l[2] < lo[2] + ext[2]; ++l[2])
+      for (l[1] = lo[1]; l[1] < lo[1] + ext[1]; ++l[1])
+        for (l[0] = lo[0]; l[0] < lo[0] + ext[0]; ++l[0]) {
+          int dist = 0;
+          for (int m = 0; m < 4; ++m)
+            if (part[m]) dist += std::max(0, std::max(-l[m], l[m] - (sub[m] - 1)));
+          const int par = (l[0] + l[1] + l[2] + l[3]) & 1;
+          const int64_t bi = box_index(l);
+          const short4 c = make_short4((short)l[0], (short)l[1], (short)l[2], (short)l[3]);
+          if (dist == 0 && par == 0) { H.C.index[bi] = (int)H.C.coords.size(); H.C.coords.push_back(c); }
+          if (dist <= 1 && par == 1) { H.N1.index[bi] = (int)H.N1.coords.size(); H.N1.coords.push_back(c); }
+          if (dist <= 2 && par == 0) { H.N2.index[bi] = (int)H.N2.coords.size(); H.N2.coords.push_back(c); }
+        }
+  auto neighbours = [&](const Region& out, const Region& in) {
+    std::vector<int> nb(out.coords.size() * 8, -1);
+    for (size_t j = 0; j < out.coords.size(); ++j) {
+      const short4 c = out.coords[j];
+      for (int mu = 0; mu < 4; ++mu)
+        for (int dir = 0; dir < 2; ++dir) {
+          int n[4] = {c.x, c.y, c.z, c.w};
+          n[mu] += dir == 0 ? 1 : -1;
+          if (!part[mu]) n[mu] = (n[mu] + dims[mu]) % dims[mu];
+          else if (n[mu] < lo[mu] || n[mu] >= lo[mu] + ext[mu]) continue;
+          nb[j * 8 + 2 * mu + dir] = in.index[box_index(n)];
+        }
+    }
+    return nb;
+  };
+  H.nbr1 = neighbours(H.N1, H.C);
+  H.nbr2 = neighbours(H.N2, H.N1);
+  H.nbr3 = neighbours(H.N1, H.N2);
+  H.nbr4 = neighbours(H.C, H.N1);
+  H.wmap2.resize(H.N2.coords.size());
+  for (size_t j = 0; j < H.N2.coords.size(); ++j) {
+    const short4 c = H.N2.coords[j];
+    int l2[4] = {c.x, c.y, c.z, c.w};
+    H.wmap2[j] = H.C.index[box_index(l2)];
+  }
+  H.wmap4.resize(H.C.coords.size());
+  for (size_t j = 0; j < H.C.coords.size(); ++j) {
+    const short4 c = H.C.coords[j];
+    int l2[4] = {c.x, c.y, c.z, c.w};
+    H.wmap4[j] = H.N2.index[box_index(l2)];
+  }
+  return H;
+}
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+// ==========================================================================
+// the handle
+// ==========================================================================
+struct mspcg_ctx {
+  int dims[4];
+  int device;
+  Lattice lat;
+  bool hip_ready = false;
+  hipStream_t stream = nullptr;
+
+  DevBuf gauge64, gauge32;
+  bool have_gauge = false;
+
+  int Ls = 0;
+  double b = 0, c = 0, M5 = 0, mf = 0;
+  bool have_params = false;
+  DevBuf mats64, mats32;
+
+  int sub[4] = {0, 0, 0, 0};
+  bool have_tiling = false;
+  int nsub = 0, nblk[4] = {1, 1, 1, 1};
+  int nC = 0, nN1 = 0, nN2 = 0;
+  DevBuf tb_cC, tb_cN1, tb_cN2, tb_nbr1, tb_nbr2, tb_nbr3, tb_nbr4, tb_w2, tb_w4;
+
+  mspcg_solver_params sp;
+  bool have_solver = false;
+
+  std::map<std::string, std::unique_ptr<DevBuf>> ws;
+  double* h_scal = nullptr;   // pinned
+
+  bool profiling = false;
+  std::vector<EventPair> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_log;   // (kind, pool index)
+
+  mspcg_ctx(const int32_t* d, int dev) {
+    for (int m = 0; m < 4; ++m) dims[m] = d[m];
+    device = dev;
+    lat.X = d[0];
+    lat.Y = d[1];
+    lat.Z = d[2];
+    lat.T = d[3];
+    lat.vh = (int64_t)d[0] * d[1] * d[2] * d[3] / 2;
+    sp.tol = 1e-10;
+    sp.maxiter = 10000;
+    sp.inner_iters = 6;
+    sp.inner_prec = MSPCG_FP16;
+    sp.outer_prec = MSPCG_FP32;
+    sp.reliable_delta = 0.1;
+    sp.beta_rule = 0;
+    sp.use_precond = 1;
+  }
+  ~mspcg_ctx() {
+    if (hip_ready) {
+      (void)hipSetDevice(device);
+      (void)hipStreamSynchronize(stream);
+      for (auto& e : ev_pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+      }
+      ws.clear();
+      if (h_scal) (void)hipHostFree(h_scal);
+      (void)hipStreamDestroy(stream);
+    }
+  }
+
+  void ensure_hip() {
+    HIPCHK(hipSetDevice(device));
+    if (hip_ready) return;
+    HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    HIPCHK(hipHostMalloc((void**)&h_scal, SLOT_COUNT * sizeof(double), hipHostMallocDefault));
+    hip_ready = true;
+  }
+
+  DevBuf& buf(const std::string& key, size_t bytes) {
+    auto& p = ws[key];
+    if (!p) p.reset(new DevBuf());
+    p->ensure(bytes);
+    return *p;
+  }
+
+  int64_t n5() const { return lat.vh * Ls; }
+
+  FieldPtr field(const std::string& key, Prec p, int64_t nsites) {
+    const int64_t n = nsites * Ls;
+    FieldPtr f;
+    f.prec = p;
+    f.stride = n;
+    DevBuf& d = buf(key, (size_t)n * chunk_bytes(p));
+    f.data = d.p;
+    if (p == Prec::F16 || p == Prec::BF16) f.scale = buf(key + ".scale", (size_t)n * sizeof(float)).as<float>();
+    return f;
+  }
+
+  const void* mat(Prec p, int id) const {
+    const size_t off = (size_t)id * 2 * Ls * Ls;
+    if (p == Prec::F64) return mats64.as<double>() + off;
+    return mats32.as<float>() + off;
+  }
+  const void* gauge(Prec p) const { return p == Prec::F64 ? gauge64.p : gauge32.p; }
+
+  double* partial(const std::string& key, int64_t n) { return buf("partial." + key, (size_t)n * sizeof(double)).as<double>(); }
+  double* scal() { return buf("scalars", SLOT_COUNT * sizeof(double)).as<double>(); }
+
+  void invalidate_workspace() {
+    if (hip_ready) HIPCHK(hipStreamSynchronize(stream));
+    ws.clear();
+  }
+
+  // ---------------------------------------------------------------- profiling
+  size_t ev_begin(hipStream_t st, int kind) {
+    if (!profiling) return (size_t)-1;
+    if (ev_used == ev_pool.size()) {
+      EventPair e;
+      HIPCHK(hipEventCreate(&e.a));
+      HIPCHK(hipEventCreate(&e.b));
+      ev_pool.push_back(e);
+    }
+    const size_t i = ev_used++;
+    HIPCHK(hipEventRecord(ev_pool[i].a, st));
+    ev_log.push_back({kind, i});
+    return i;
+  }
+  void ev_end(hipStream_t st, size_t i) {
+    if (i == (size_t)-1) return;
+    HIPCHK(hipEventRecord(ev_pool[i].b, st));
+  }
+
+  // ---------------------------------------------------------------- tables
+  SubTables tables(int which, Prec p) const {
+    SubTables t;
+    std::memset(&t, 0, sizeof(t));
+    for (int m = 0; m < 4; ++m) {
+      t.sub[m] = sub[m];
+      t.dims[m] = dims[m];
+      t.nblk[m] = nblk[m];
+    }
+    const int ns = sites_per_block(Ls, p);
+    switch (which) {
+      case 0:   // C (restrict / update / prolong)
+        t.coords = tb_cC.as<short4>(); t.nbr = nullptr; t.wmap = nullptr;
+        t.n_out = nC; t.n_in = nC; t.n_w = nC; break;
+      case 1:   // h1: N1 <- C
+        t.coords = tb_cN1.as<short4>(); t.nbr = tb_nbr1.as<int>(); t.wmap = nullptr;
+        t.n_out = nN1; t.n_in = nC; t.n_w = nN1; break;
+      case 2:   // h2: N2 <- N1, centre field on C
+        t.coords = tb_cN2.as<short4>(); t.nbr = tb_nbr2.as<int>(); t.wmap = tb_w2.as<int>();
+        t.n_out = nN2; t.n_in = nN1; t.n_w = nC; break;
+      case 3:   // h3: N1 <- N2
+        t.coords = tb_cN1.as<short4>(); t.nbr = tb_nbr3.as<int>(); t.wmap = nullptr;
+        t.n_out = nN1; t.n_in = nN2; t.n_w = nN1; break;
+      case 4:   // h4: C <- N1, centre field on N2
+        t.coords = tb_cC.as<short4>(); t.nbr = tb_nbr4.as<int>(); t.wmap = tb_w4.as<int>();
+        t.n_out = nC; t.n_in = nN1; t.n_w = nN2; break;
+    }
+    t.bps = (t.n_out + ns - 1) / ns;
+    return t;
+  }
+
+  // ---------------------------------------------------------------- operators
+  void hop(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int out_par, bool dag,
+           const Epilogue& epi) {
+    HopGeometry g;
+    g.lat = lat;
+    g.out_parity = out_par;
+    g.Ls = Ls;
+    const size_t e = ev_begin(st, 0);
+    hop_full(st, p, out, in, w, gauge(p), g, dag, epi);
+    ev_end(st, e);
+  }
+
+  Epilogue epi(Prec p, int e0, int e1, int e2, bool wid = false, double* norm = nullptr) const {
+    Epilogue E;
+    E.E0 = e0 >= 0 ? mat(p, e0) : nullptr;
+    E.E1 = e1 >= 0 ? mat(p, e1) : nullptr;
+    E.E2 = e2 >= 0 ? mat(p, e2) : nullptr;
+    E.w_identity = wid;
+    E.norm_partial = norm;
+    return E;
+  }
+
+  // A = D^dag D on p, given t0 = M_phi p.  norm_partial gets |D p|^2 = <p, A p>.
+  void A_from_t0(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr& t0,
+                 const std::string& tag, double* norm_partial) {
+    FieldPtr a = field(tag + ".a", p, lat.vh), c = field(tag + ".c", p, lat.vh), e = field(tag + ".e", p, lat.vh);
+    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q, -1));
+    hop(st, p, c, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, MAT_M5INV_T, true, norm_partial));
+    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT, -1));
+    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, -1));
+  }
+
+  void A_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag,
+            double* norm_partial) {
+    FieldPtr t0 = field(tag + ".t0", p, lat.vh);
+    apply5_full(st, p, t0, in, mat(p, MAT_MPHI), lat.vh, Ls, nullptr);
+    A_from_t0(st, p, out, in, t0, tag, norm_partial);
+  }
+
+  void D_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag) {
+    FieldPtr t0 = field(tag + ".t0", p, lat.vh), a = field(tag + ".a", p, lat.vh);
+    apply5_full(st, p, t0, in, mat(p, MAT_MPHI), lat.vh, Ls, nullptr);
+    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q, -1));
+    hop(st, p, out, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, -1, true));
+  }
+
+  void Ddag_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag) {
+    FieldPtr t0 = field(tag + ".t0", p, lat.vh), e = field(tag + ".e", p, lat.vh);
+    apply5_full(st, p, t0, in, mat(p, MAT_M5INV_T), lat.vh, Ls, nullptr);
+    hop(st, p, e, t0, nullptr, 1, true, epi(p, -1, MAT_QT, -1));
+    hop(st, p, out, e, &in, 0, true, epi(p, -1, MAT_NEG_MPHI_T, -1, true));
+  }
+
+  // A_s p_s for every subdomain (inner storage I), given t0 = M_phi p_s on C.
+  // pAp partials [d][bps of h2] when norm != null.
+  void Asub(hipStream_t st, Prec I, const FieldPtr& q, const FieldPtr& ps, const FieldPtr& t0, double* norm) {
+    FieldPtr a = field("in.a", I, (int64_t)nsub * nN1), c = field("in.c", I, (int64_t)nsub * nN2),
+             e = field("in.e", I, (int64_t)nsub * nN1);
+    auto run = [&](int which, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int par, bool dag,
+                   const Epilogue& E) {
+      const size_t ev = ev_begin(st, 1);
+      hop_sub(st, I, out, in, w, gauge(I), lat, par, tables(which, I), nsub, Ls, dag, E);
+      ev_end(st, ev);
+    };
+    run(1, a, t0, nullptr, 1, false, epi(I, -1, MAT_Q, -1));
+    run(2, c, a, &ps, 0, false, epi(I, -1, MAT_NEG_M5INV, MAT_M5INV_T, true, norm));
+    run(3, e, c, nullptr, 1, true, epi(I, -1, MAT_QT, -1));
+    run(4, q, e, &c, 0, true, epi(I, MAT_M5_T, MAT_NEG_MPHI_T, -1));
+  }
+
+  // z = (+)_s CG_k(A_s, R_s r).  Outer precision O for r, z, r_old.
+  // dots: partials of <z, r> and <z, r_old> into pz1/pz2 (nsub * bpsC entries).
+  int precondition(hipStream_t st, Prec O, Prec I, const FieldPtr& z, const FieldPtr& r, const FieldPtr* rold,
+                   int k, double* pz1, double* pz2) {
+    const size_t ev = ev_begin(st, 2);
+    const int64_t nc = (int64_t)nsub * nC;
+    FieldPtr rs = field("in.r", I, nc), ps = field("in.p", I, nc), zs = field("in.z", I, nc),
+             qs = field("in.q", I, nc), t0 = field("in.t0", I, nc);
+    SubScalars sc;
+    sc.rho = buf("in.rho", nsub * sizeof(double)).as<double>();
+    sc.alpha = buf("in.alpha", nsub * sizeof(double)).as<double>();
+    sc.beta = buf("in.beta", nsub * sizeof(double)).as<double>();
+    sc.active = buf("in.active", nsub * sizeof(int)).as<int>();
+    const SubTables tc = tables(0, I), t2 = tables(2, I);
+    double* prr = partial("in.rr", (int64_t)nsub * tc.bps);
+    double* ppap = partial("in.pap", (int64_t)nsub * t2.bps);
+    sub_restrict(st, O, I, r, rs, ps, t0, mat(I, MAT_MPHI), lat, tc, nsub, Ls, prr);
+    sub_finish(st, prr, tc.bps, nsub, sc, SUB_INIT);
+    for (int it = 0; it < k; ++it) {
+      if (it > 0) sub_xpay5(st, I, ps, rs, t0, sc, mat(I, MAT_MPHI), tc, nsub, Ls);
+      Asub(st, I, qs, ps, t0, ppap);
+      sub_finish(st, ppap, t2.bps, nsub, sc, SUB_ALPHA);
+      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, prr);
+      sub_finish(st, prr, tc.bps, nsub, sc, SUB_BETA);
+    }
+    sub_prolong(st, O, I, z, zs, r, rold, lat, tc, nsub, Ls, pz1, pz2);
+    ev_end(st, ev);
+    return k;
+  }
+};
+
+// ==========================================================================
+// solver
+// ==========================================================================
+namespace {
+
+void read_scalars(mspcg_ctx* h, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(h->h_scal, h->scal(), SLOT_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const double* x0_dev, hipStream_t st,
+                        mspcg_stats* stats) {
+  const mspcg_solver_params& sp = h->sp;
+  const Prec O = to_prec(sp.outer_prec);
+  const Prec I = to_prec(sp.inner_prec);
+  const bool pre = sp.use_precond != 0;
+  const bool pr = sp.beta_rule == 0;
+  const int64_t vh = h->lat.vh, n5 = h->n5(), nreal = n5 * 24;
+  const int Ls = h->Ls;
+  if (pre && !h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "MSPCG needs mspcg_set_subdomains");
+  if (pre && sp.inner_iters < 1) throw Error(MSPCG_ERR_INVALID_ARG, "MSPCG needs inner_iters >= 1");
+
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, st));
+
+  double* scal = h->scal();
+  const int64_t nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4));
+  const int64_t nbl64 = blas_blocks(nreal / 2);
+  double* p_upd = h->partial("upd", nbl);
+  double* p_ru = h->partial("ru", nbl64);
+  double* p_b = h->partial("b", nbl64);
+  const int64_t bps_hop = full_blocks(vh, Ls, O);
+  double* p_pap = h->partial("pap", bps_hop);
+  int64_t nz = 0;
+  double *p_z1 = nullptr, *p_z2 = nullptr;
+  if (pre) {
+    nz = (int64_t)h->nsub * h->tables(0, I).bps;
+    p_z1 = h->partial("z1", nz);
+    p_z2 = h->partial("z2", nz);
+  } else {
+    p_z1 = h->partial("z1", nbl);
+  }
+
+  // FP64 copies: b, x_hi, r64, A64 workspace output
+  FieldPtr b64 = h->field("s.b64", Prec::F64, vh), x64 = h->field("s.x64", Prec::F64, vh);
+  FieldPtr r64 = h->field("s.r64", Prec::F64, vh), q64 = h->field("s.q64", Prec::F64, vh);
+  pack_field(st, b64, b_dev, vh, Ls);
+  if (x0_dev) pack_field(st, x64, x0_dev, vh, Ls);
+  else HIPCHK(hipMemsetAsync(x64.data, 0, (size_t)n5 * 192, st));
+
+  // outer vectors
+  FieldPtr x = O == Prec::F64 ? x64 : h->field("s.x", O, vh);
+  FieldPtr rA = h->field("s.rA", O, vh);
+  FieldPtr rB = h->field("s.rB", O, vh);
+  FieldPtr z = pre ? h->field("s.z", O, vh) : rA;
+  FieldPtr p = h->field("s.p", O, vh), q = h->field("s.q", O, vh), t0 = h->field("s.t0", O, vh);
+  if (O == Prec::F32) HIPCHK(hipMemsetAsync(x.data, 0, (size_t)n5 * 96, st));
+  HIPCHK(hipMemsetAsync(p.data, 0, (size_t)n5 * chunk_bytes(O), st));
+
+  // |b|^2
+  dot2(st, Prec::F64, b64.data, b64.data, nullptr, nreal, p_b, nullptr, nbl64);
+  finish(st, p_b, nullptr, nbl64, scal, FIN_STORE, SLOT_TMP);
+  read_scalars(h, st);
+  const double bnorm2 = h->h_scal[SLOT_TMP];
+  if (!std::isfinite(bnorm2)) throw Error(MSPCG_ERR_BREAKDOWN, "source is not finite");
+  const double bnorm = std::sqrt(bnorm2);
+
+  FieldPtr* r = &rA;
+  FieldPtr* rold = &rB;
+
+  // true residual r = b - A x (FP64), lower precision copy into r
+  auto true_residual = [&]() -> double {
+    h->A_op(st, Prec::F64, q64, x64, "A64", nullptr);
+    residual64(st, b64.data ? (const double*)b64.data : nullptr, (const double*)q64.data, (double*)r64.data,
+               O == Prec::F32 ? (float*)r->data : nullptr, n5, p_ru, nbl64);
+    if (O == Prec::F64 && r->data != r64.data)
+      HIPCHK(hipMemcpyAsync(r->data, r64.data, (size_t)n5 * 192, hipMemcpyDeviceToDevice, st));
+    finish(st, p_ru, nullptr, nbl64, scal, FIN_STORE, SLOT_R64);
+    read_scalars(h, st);
+    return h->h_scal[SLOT_R64];
+  };
+
+  mspcg_stats S;
+  std::memset(&S, 0, sizeof(S));
+  mspcg_status status = MSPCG_NOT_CONVERGED;
+  if (bnorm2 == 0.0) {
+    HIPCHK(hipMemsetAsync(x64.data, 0, (size_t)n5 * 192, st));
+    status = MSPCG_OK;
+  } else {
+    double rr = x0_dev ? true_residual() : bnorm2;
+    if (!x0_dev) {
+      // r = b
+      if (O == Prec::F64) HIPCHK(hipMemcpyAsync(r->data, b64.data, (size_t)n5 * 192, hipMemcpyDeviceToDevice, st));
+      else f64_to_f32(st, (const double*)b64.data, (float*)r->data, n5);
+      HIPCHK(hipMemcpyAsync(r64.data, b64.data, (size_t)n5 * 192, hipMemcpyDeviceToDevice, st));
+    }
+    double rmax = std::sqrt(rr);
+    const double delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.0;
+    const double* rr_partial = nullptr;
+
+    // z = M r ; rho = <r, z>
+    auto apply_precond = [&](bool with_rold) {
+      if (pre) {
+        h->precondition(st, O, I, z, *r, with_rold ? rold : nullptr, sp.inner_iters, p_z1, p_z2);
+        S.inner_iters_total += sp.inner_iters;
+      }
+    };
+    apply_precond(false);
+    if (pre) finish(st, p_z1, nullptr, nz, scal, FIN_RHO, 0);
+    else {
+      dot2(st, O, r->data, r->data, nullptr, nreal, p_z1, nullptr, nbl);
+      finish(st, p_z1, nullptr, nbl, scal, FIN_RHO, 0);
+    }
+    // p = z ; t0 = M_phi p   (p is zero, beta slot holds 0)
+    HIPCHK(hipMemsetAsync(scal + SLOT_TMP, 0, sizeof(double), st));
+    xpay_apply5(st, O, t0, p, z, scal, SLOT_TMP, h->mat(O, MAT_MPHI), vh, Ls);
+
+    int it = 0;
+    while (true) {
+      // q = A p, <p, A p> = |D p|^2
+      h->A_from_t0(st, O, q, p, t0, "Aout", p_pap);
+      finish(st, p_pap, nullptr, bps_hop, scal, FIN_ALPHA, 0);
+      // x += alpha p ; r_new = r - alpha q
+      cg_update(st, O, x.data, p.data, r->data, q.data, rold->data, nreal, scal, SLOT_ALPHA, p_upd, nbl);
+      std::swap(r, rold);   // r: new residual, rold: previous
+      finish(st, p_upd, nullptr, nbl, scal, FIN_STORE, SLOT_RR);
+      rr_partial = p_upd;
+      read_scalars(h, st);
+      ++it;
+      const double pap = h->h_scal[SLOT_PAP];
+      rr = h->h_scal[SLOT_RR];
+      if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(rr)) {
+        status = MSPCG_ERR_BREAKDOWN;
+        S.iter_rel_resid = std::sqrt(std::fabs(rr)) / bnorm;
+        break;
+      }
+      const double rn = std::sqrt(rr);
+      S.iter_rel_resid = rn / bnorm;
+      rmax = std::max(rmax, rn);
+      const bool conv = rn <= sp.tol * bnorm;
+      const bool last = it >= sp.maxiter;
+      const bool ru = conv || last || (delta > 0 && rn < delta * rmax);
+      if (ru) {
+        if (O == Prec::F32) accum_lo(st, (double*)x64.data, (float*)x.data, n5);
+        // keep the previous residual's copy: with FP32 the new residual
+        // overwrites *r in place, r_old is untouched
+        rr = true_residual();
+        rr_partial = p_ru;
+        ++S.reliable_updates;
+        rmax = std::sqrt(rr);
+        S.iter_rel_resid = std::sqrt(rr) / bnorm;
+        if (std::sqrt(rr) <= sp.tol * bnorm) { status = MSPCG_OK; break; }
+        if (!std::isfinite(rr)) { status = MSPCG_ERR_BREAKDOWN; break; }
+      }
+      if (last) { status = MSPCG_NOT_CONVERGED; break; }
+      // z = M r ; beta
+      if (pre) {
+        apply_precond(pr);
+        finish(st, p_z1, pr ? p_z2 : nullptr, nz, scal, pr ? FIN_BETA_PR : FIN_BETA_FR, 0);
+      } else {
+        if (pr) {
+          dot2(st, O, r->data, r->data, rold->data, nreal, p_z1, p_z2 ? p_z2 : h->partial("z2", nbl), nbl);
+          finish(st, p_z1, h->partial("z2", nbl), nbl, scal, FIN_BETA_PR, 0);
+        } else {
+          finish(st, rr_partial, nullptr, rr_partial == p_ru ? nbl64 : nbl, scal, FIN_BETA_FR, 0);
+        }
+      }
+      // p = z + beta p ; t0 = M_phi p
+      xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_BETA, h->mat(O, MAT_MPHI), vh, Ls);
+    }
+    S.outer_iters = it;
+    if (O == Prec::F32 && status != MSPCG_OK && status != MSPCG_ERR_BREAKDOWN) {
+      // x_hi already holds the accumulated solution after the final reliable update
+    }
+    S.true_rel_resid = std::sqrt(std::fabs(rr)) / bnorm;
+  }
+  unpack_field(st, x_dev, x64, vh, Ls);
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  S.ms_total = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (h->profiling) {
+    double tot = 0;
+    for (auto& kv : h->ev_log)
+      if (kv.first == 2) {
+        float m = 0;
+        if (hipEventElapsedTime(&m, h->ev_pool[kv.second].a, h->ev_pool[kv.second].b) == hipSuccess) tot += m;
+      }
+    S.ms_precond = tot;
+  }
+  if (stats) *stats = S;
+  return status;
+}
+
+void apply_impl(mspcg_ctx* h, int op, Prec P, const double* in_dev, double* out_dev, hipStream_t st) {
+  const int64_t vh = h->lat.vh;
+  const int Ls = h->Ls;
+  if (op == MSPCG_OP_A_SUB || op == MSPCG_OP_PRECOND) {
+    if (!h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "operator needs mspcg_set_subdomains");
+    const Prec O = (P == Prec::F64) ? Prec::F64 : Prec::F32;
+    FieldPtr fi = h->field("ap.in", O, vh), fo = h->field("ap.out", O, vh);
+    pack_field(st, fi, in_dev, vh, Ls);
+    const SubTables tc = h->tables(0, P);
+    const int64_t nz = (int64_t)h->nsub * tc.bps;
+    double* p1 = h->partial("ap.z1", nz);
+    double* p2 = h->partial("ap.z2", nz);
+    if (op == MSPCG_OP_PRECOND) {
+      h->precondition(st, O, P, fo, fi, nullptr, h->sp.inner_iters, p1, p2);
+    } else {
+      const int64_t nc = (int64_t)h->nsub * h->nC;
+      FieldPtr rs = h->field("in.r", P, nc), ps = h->field("in.p", P, nc), t0 = h->field("in.t0", P, nc),
+               qs = h->field("in.q", P, nc);
+      sub_restrict(st, O, P, fi, rs, ps, t0, h->mat(P, MAT_MPHI), h->lat, tc, h->nsub, Ls, p1);
+      h->Asub(st, P, qs, ps, t0, nullptr);
+      sub_prolong(st, O, P, fo, qs, fi, nullptr, h->lat, tc, h->nsub, Ls, p1, p2);
+    }
+    unpack_field(st, out_dev, fo, vh, Ls);
+    return;
+  }
+  FieldPtr fi = h->field("ap.in", P, vh), fo = h->field("ap.out", P, vh);
+  pack_field(st, fi, in_dev, vh, Ls);
+  switch (op) {
+    case MSPCG_OP_DSLASH_EO: h->hop(st, P, fo, fi, nullptr, 0, false, Epilogue()); break;
+    case MSPCG_OP_DSLASH_OE: h->hop(st, P, fo, fi, nullptr, 1, false, Epilogue()); break;
+    case MSPCG_OP_DSLASH_DAG_EO: h->hop(st, P, fo, fi, nullptr, 0, true, Epilogue()); break;
+    case MSPCG_OP_DSLASH_DAG_OE: h->hop(st, P, fo, fi, nullptr, 1, true, Epilogue()); break;
+    case MSPCG_OP_M5: apply5_full(st, P, fo, fi, h->mat(P, MAT_M5), vh, Ls, nullptr); break;
+    case MSPCG_OP_M5INV: apply5_full(st, P, fo, fi, h->mat(P, MAT_M5INV), vh, Ls, nullptr); break;
+    case MSPCG_OP_MPHI: apply5_full(st, P, fo, fi, h->mat(P, MAT_MPHI), vh, Ls, nullptr); break;
+    case MSPCG_OP_D: h->D_op(st, P, fo, fi, "ap"); break;
+    case MSPCG_OP_DDAG: h->Ddag_op(st, P, fo, fi, "ap"); break;
+    case MSPCG_OP_A: h->A_op(st, P, fo, fi, "ap", nullptr); break;
+    default: throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
+  }
+  unpack_field(st, out_dev, fo, vh, Ls);
+}
+
+void need_state(mspcg_ctx* h) {
+  if (!h->have_gauge) throw Error(MSPCG_ERR_NO_GAUGE, "no gauge field loaded");
+  if (!h->have_params) throw Error(MSPCG_ERR_NO_PARAMS, "Mobius parameters not set");
+}
+
+template <typename F> mspcg_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MSPCG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MSPCG_ERR_HIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return MSPCG_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+mspcg_status mspcg_create(mspcg_t* out, const int32_t dims[4], int32_t device) {
+  return guarded([&]() -> mspcg_status {
+    if (!out || !dims) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    for (int m = 0; m < 4; ++m)
+      if (dims[m] < 2 || dims[m] % 2 || dims[m] > 32000) throw Error(MSPCG_ERR_INVALID_ARG, "lattice extents must be even and >= 2");
+    if (device < 0) throw Error(MSPCG_ERR_INVALID_ARG, "device must be >= 0");
+    *out = new mspcg_ctx(dims, device);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_destroy(mspcg_t h) {
+  return guarded([&]() -> mspcg_status {
+    delete h;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !U) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    h->ensure_hip();
+    hipStream_t st = h->stream;
+    const int64_t V = 2 * h->lat.vh;
+    const size_t canon = (size_t)V * 4 * 9 * 2 * sizeof(double);
+    DevBuf stage;
+    stage.ensure(canon);
+    HIPCHK(hipMemcpyAsync(stage.p, U, canon, hipMemcpyHostToDevice, st));
+    h->gauge64.ensure((size_t)V * 4 * 9 * sizeof(double2));
+    h->gauge32.ensure((size_t)V * 4 * 9 * sizeof(float2));
+    pack_gauge(st, h->gauge64.p, true, stage.as<double>(), h->lat);
+    pack_gauge(st, h->gauge32.p, false, stage.as<double>(), h->lat);
+    HIPCHK(hipStreamSynchronize(st));
+    h->have_gauge = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double M5, double mf) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (Ls < 2 || Ls > 32) throw Error(MSPCG_ERR_INVALID_ARG, "Ls must be in [2, 32]");
+    if (!std::isfinite(b) || !std::isfinite(c) || !std::isfinite(M5) || !std::isfinite(mf))
+      throw Error(MSPCG_ERR_INVALID_ARG, "non-finite Mobius parameter");
+    Mats M = build_mats(Ls, b, c, M5, mf);
+    h->ensure_hip();
+    h->invalidate_workspace();
+    std::vector<float> m32(M.m.begin(), M.m.end());
+    h->mats64.ensure(M.m.size() * sizeof(double));
+    h->mats32.ensure(m32.size() * sizeof(float));
+    HIPCHK(hipMemcpy(h->mats64.p, M.m.data(), M.m.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->mats32.p, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice));
+    h->Ls = Ls;
+    h->b = b;
+    h->c = c;
+    h->M5 = M5;
+    h->mf = mf;
+    h->have_params = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !sub) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    int s[4] = {sub[0], sub[1], sub[2], sub[3]};
+    std::string why;
+    if (!tiling_valid(h->dims, s, why)) throw Error(MSPCG_ERR_BAD_TILING, why);
+    HostTables H = build_tables(h->dims, s);
+    h->ensure_hip();
+    h->invalidate_workspace();
+    auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+      d.ensure(bytes);
+      if (bytes) HIPCHK(hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice));
+    };
+    up(h->tb_cC, H.C.coords.data(), H.C.coords.size() * sizeof(short4));
+    up(h->tb_cN1, H.N1.coords.data(), H.N1.coords.size() * sizeof(short4));
+    up(h->tb_cN2, H.N2.coords.data(), H.N2.coords.size() * sizeof(short4));
+    up(h->tb_nbr1, H.nbr1.data(), H.nbr1.size() * sizeof(int));
+    up(h->tb_nbr2, H.nbr2.data(), H.nbr2.size() * sizeof(int));
+    up(h->tb_nbr3, H.nbr3.data(), H.nbr3.size() * sizeof(int));
+    up(h->tb_nbr4, H.nbr4.data(), H.nbr4.size() * sizeof(int));
+    up(h->tb_w2, H.wmap2.data(), H.wmap2.size() * sizeof(int));
+    up(h->tb_w4, H.wmap4.data(), H.wmap4.size() * sizeof(int));
+    h->nC = (int)H.C.coords.size();
+    h->nN1 = (int)H.N1.coords.size();
+    h->nN2 = (int)H.N2.coords.size();
+    h->nsub = 1;
+    for (int m = 0; m < 4; ++m) {
+      h->sub[m] = s[m];
+      h->nblk[m] = h->dims[m] / s[m];
+      h->nsub *= h->nblk[m];
+    }
+    h->have_tiling = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_solver(mspcg_t h, const mspcg_solver_params* p) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !p) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (!(p->tol > 0) || p->maxiter < 1 || p->inner_iters < 0 || p->inner_iters > 1000)
+      throw Error(MSPCG_ERR_INVALID_ARG, "tol > 0, maxiter >= 1, 0 <= inner_iters <= 1000 required");
+    if (p->outer_prec != MSPCG_FP64 && p->outer_prec != MSPCG_FP32)
+      throw Error(MSPCG_ERR_INVALID_ARG, "outer precision must be FP64 or FP32");
+    (void)to_prec(p->inner_prec);
+    if (p->beta_rule != 0 && p->beta_rule != 1) throw Error(MSPCG_ERR_INVALID_ARG, "beta_rule must be 0 or 1");
+    if (!(p->reliable_delta >= 0) || p->reliable_delta >= 1) throw Error(MSPCG_ERR_INVALID_ARG, "reliable_delta in [0, 1)");
+    h->sp = *p;
+    h->have_solver = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const double* x0, void* hip_stream,
+                                mspcg_stats* st) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    need_state(h);
+    h->ensure_hip();
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
+    return solve_impl(h, b, x, x0, s, st);
+  });
+}
+
+mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0, mspcg_stats* st) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    need_state(h);
+    h->ensure_hip();
+    const size_t bytes = (size_t)h->n5() * 24 * sizeof(double);
+    DevBuf db, dx, dx0;
+    db.ensure(bytes);
+    dx.ensure(bytes);
+    HIPCHK(hipMemcpyAsync(db.p, b, bytes, hipMemcpyHostToDevice, h->stream));
+    if (x0) {
+      dx0.ensure(bytes);
+      HIPCHK(hipMemcpyAsync(dx0.p, x0, bytes, hipMemcpyHostToDevice, h->stream));
+    }
+    mspcg_status r = solve_impl(h, db.as<double>(), dx.as<double>(), x0 ? dx0.as<double>() : nullptr, h->stream, st);
+    HIPCHK(hipMemcpyAsync(x, dx.p, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return r;
+  });
+}
+
+mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
+                                void* hip_stream) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_PRECOND) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
+    const Prec P = to_prec(prec);
+    need_state(h);
+    h->ensure_hip();
+    apply_impl(h, op, P, in, out, hip_stream ? (hipStream_t)hip_stream : h->stream);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_PRECOND) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
+    const Prec P = to_prec(prec);
+    need_state(h);
+    h->ensure_hip();
+    const size_t bytes = (size_t)h->n5() * 24 * sizeof(double);
+    DevBuf di, dout;
+    di.ensure(bytes);
+    dout.ensure(bytes);
+    HIPCHK(hipMemcpyAsync(di.p, in, bytes, hipMemcpyHostToDevice, h->stream));
+    apply_impl(h, op, P, di.as<double>(), dout.as<double>(), h->stream);
+    HIPCHK(hipMemcpyAsync(out, dout.p, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_profiling(mspcg_t h, int32_t on) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (h->hip_ready) HIPCHK(hipStreamSynchronize(h->stream));
+    h->profiling = on != 0;
+    h->ev_used = 0;
+    h->ev_log.clear();
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, double* ms) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !launches || !ms) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    *launches = 0;
+    *ms = 0;
+    if (!h->hip_ready) return MSPCG_OK;
+    HIPCHK(hipDeviceSynchronize());
+    for (auto& kv : h->ev_log) {
+      if (kv.first != kind) continue;
+      float m = 0;
+      HIPCHK(hipEventElapsedTime(&m, h->ev_pool[kv.second].a, h->ev_pool[kv.second].b));
+      *ms += m;
+      ++*launches;
+    }
+    return MSPCG_OK;
+  });
+}
+
+const char* mspcg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+// Preconditioner kernels (Sec. 2.4-2.5): moving the outer residual into the
+// centre region C of every virtual subdomain and the inner solution back, and
+// the inner CG's vector updates with per-subdomain scalars.  The four hops of
+// the local operator A_s run through hop_sub (kernels.hip).
+//
+// All kernels here map threads like the site kernels: a block owns ns sites
+// of C of one subdomain and all their Ls slices, so per-block partial sums are
+// grouped by subdomain as [d][bps].
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+#include "sitekern.h"
+
+namespace mspcg {
+
+#define LAUNCH_CHECK()                                                                \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("kernel launch: ") +   \
+                                                   hipGetErrorString(e_));            \
+  } while (0)
+
+struct CSite {
+  bool inb, valid;
+  int sl, s;
+  int64_t blk, d, j, in5;   // in5: index in the per-subdomain C field
+};
+
+__device__ __forceinline__ CSite c_site(const SubTables& tc, int ns, int Ls) {
+  CSite c;
+  const int tid = threadIdx.x;
+  c.inb = tid < ns * Ls;
+  c.sl = c.inb ? tid / Ls : 0;
+  c.s = c.inb ? tid - c.sl * Ls : 0;
+  c.blk = xcd_block(blockIdx.x, gridDim.x);
+  c.d = c.blk / tc.bps;
+  c.j = (c.blk - c.d * tc.bps) * ns + c.sl;
+  c.valid = c.inb && c.j < tc.n_out;
+  c.in5 = (c.d * tc.n_out + c.j) * Ls + c.s;
+  return c;
+}
+
+// global single-parity index of centre site j of subdomain d
+__device__ __forceinline__ int64_t c_global(const SubTables& tc, const Lattice& lat, int64_t d, int64_t j) {
+  const short4 lc = tc.coords[j];
+  int64_t q = d;
+  const int b0 = (int)(q % tc.nblk[0]); q /= tc.nblk[0];
+  const int b1 = (int)(q % tc.nblk[1]); q /= tc.nblk[1];
+  const int b2 = (int)(q % tc.nblk[2]); q /= tc.nblk[2];
+  const int b3 = (int)q;
+  // centre sites lie inside the subdomain: no wrap needed
+  int g[4] = {b0 * tc.sub[0] + lc.x, b1 * tc.sub[1] + lc.y, b2 * tc.sub[2] + lc.z, b3 * tc.sub[3] + lc.w};
+  return lat.index(g);
+}
+
+template <typename O, typename I>
+__global__ void __launch_bounds__(256)
+k_sub_restrict(Field<O> r, Field<I> rs, Field<I> ps, Field<I> t0, const calc_t<I>* E, Lattice lat, SubTables tc,
+               int Ls, int ns, double* partial) {
+  using T = calc_t<I>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* red = reinterpret_cast<double*>(lds_raw);
+  T* mats = reinterpret_cast<T*>(red + 16);
+  T* tile = mats + 2 * Ls * Ls;
+  const CSite c = c_site(tc, ns, Ls);
+  for (int k = threadIdx.x; k < 2 * Ls * Ls; k += blockDim.x) mats[k] = E[k];
+  T v[24];
+  if (c.valid) {
+    const int64_t g = c_global(tc, lat, c.d, c.j);
+    load_site(r, g * Ls + c.s, v);
+    store_site(rs, c.in5, v);
+    store_site(ps, c.in5, v);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = 0;
+  }
+  double loc = 0;
+#pragma unroll
+  for (int k = 0; k < 24; ++k) loc += (double)v[k] * (double)v[k];
+  T* my = tile + c.sl * tile_stride(Ls);
+  if (c.inb) tile_put(my, c.s, v);
+  __syncthreads();
+  if (c.inb) mat5_lds(my, mats, c.s, Ls, v, false);
+  if (c.valid) store_site(t0, c.in5, v);
+  const double tot = block_sum(loc, red);
+  if (threadIdx.x == 0) partial[c.blk] = tot;
+}
+
+template <typename I>
+__global__ void __launch_bounds__(256)
+k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* alpha, int first, SubTables tc, int Ls,
+             int ns, double* partial) {
+  using T = calc_t<I>;
+  __shared__ double red[16];
+  const CSite c = c_site(tc, ns, Ls);
+  double loc = 0;
+  if (c.valid) {
+    const T a = (T)alpha[c.d];
+    T z[24], p[24], r[24], q[24];
+    load_site(ps, c.in5, p);
+    load_site(rs, c.in5, r);
+    load_site(qs, c.in5, q);
+    if (first) {
+#pragma unroll
+      for (int k = 0; k < 24; ++k) z[k] = a * p[k];
+    } else {
+      load_site(zs, c.in5, z);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) z[k] += a * p[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+      r[k] -= a * q[k];
+      loc += (double)r[k] * (double)r[k];
+    }
+    store_site(zs, c.in5, z);
+    store_site(rs, c.in5, r);
+  }
+  const double tot = block_sum(loc, red);
+  if (threadIdx.x == 0) partial[c.blk] = tot;
+}
+
+template <typename I>
+__global__ void __launch_bounds__(256)
+k_sub_xpay5(Field<I> ps, Field<I> rs, Field<I> t0, const double* beta, const calc_t<I>* E, SubTables tc, int Ls,
+            int ns) {
+  using T = calc_t<I>;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* red = reinterpret_cast<double*>(lds_raw);
+  T* mats = reinterpret_cast<T*>(red + 16);
+  T* tile = mats + 2 * Ls * Ls;
+  const CSite c = c_site(tc, ns, Ls);
+  for (int k = threadIdx.x; k < 2 * Ls * Ls; k += blockDim.x) mats[k] = E[k];
+  T p[24];
+  if (c.valid) {
+    const T b = (T)beta[c.d];
+    T r[24];
+    load_site(ps, c.in5, p);
+    load_site(rs, c.in5, r);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) p[k] = r[k] + b * p[k];
+    store_site(ps, c.in5, p);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) p[k] = 0;
+  }
+  T* my = tile + c.sl * tile_stride(Ls);
+  if (c.inb) tile_put(my, c.s, p);
+  __syncthreads();
+  if (c.inb) mat5_lds(my, mats, c.s, Ls, p, false);
+  if (c.valid) store_site(t0, c.in5, p);
+}
+
+template <typename O, typename I>
+__global__ void __launch_bounds__(256)
+k_sub_prolong(Field<O> z, Field<I> zs, Field<O> r, Field<O> rold, int has_rold, Lattice lat, SubTables tc, int Ls,
+              int ns, double* partial1, double* partial2) {
+  using T = calc_t<O>;
+  __shared__ double red[16];
+  const CSite c = c_site(tc, ns, Ls);
+  double l1 = 0, l2 = 0;
+  if (c.valid) {
+    const int64_t g5 = c_global(tc, lat, c.d, c.j) * Ls + c.s;
+    T v[24], rv[24];
+    load_site(zs, c.in5, v);
+    store_site(z, g5, v);
+    // the dots use z as stored in the outer precision
+    load_site(z, g5, v);
+    load_site(r, g5, rv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) l1 += (double)v[k] * (double)rv[k];
+    if (has_rold) {
+      load_site(rold, g5, rv);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) l2 += (double)v[k] * (double)rv[k];
+    }
+  }
+  const double t1 = block_sum(l1, red);
+  if (threadIdx.x == 0) partial1[c.blk] = t1;
+  if (has_rold) {
+    const double t2 = block_sum(l2, red);
+    if (threadIdx.x == 0) partial2[c.blk] = t2;
+  }
+}
+
+__global__ void k_sub_finish(const double* partial, int bps, int nsub, double* rho, double* alpha, double* beta,
+                             int* active, int mode) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nsub) return;
+  double S = 0;
+  for (int b = 0; b < bps; ++b) S += partial[(int64_t)d * bps + b];
+  switch (mode) {
+    case SUB_INIT:
+      rho[d] = S;
+      active[d] = S > 0.0 ? 1 : 0;
+      alpha[d] = 0.0;
+      beta[d] = 0.0;
+      break;
+    case SUB_ALPHA:
+      if (active[d] && S > 0.0 && isfinite(S)) alpha[d] = rho[d] / S;
+      else { alpha[d] = 0.0; active[d] = 0; }
+      break;
+    case SUB_BETA:
+      if (active[d] && S > 0.0) { beta[d] = S / rho[d]; rho[d] = S; }
+      else { beta[d] = 0.0; active[d] = 0; }
+      break;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int c_ns(int Ls, Prec p) { return sites_per_block(Ls, p); }
+
+template <typename O, typename I>
+static void restrict_t(hipStream_t st, const FieldPtr& r, const FieldPtr& rs, const FieldPtr& ps, const FieldPtr& t0,
+                       const void* E, const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* partial) {
+  using T = calc_t<I>;
+  const int ns = c_ns(Ls, rs.prec);
+  const size_t lds = 16 * sizeof(double) + sizeof(T) * (size_t)(2 * Ls * Ls + ns * tile_stride(Ls));
+  hipLaunchKernelGGL((k_sub_restrict<O, I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)),
+                     lds, st, typed<O>(r), typed<I>(rs), typed<I>(ps), typed<I>(t0), (const T*)E, lat, tc, Ls, ns,
+                     partial);
+  LAUNCH_CHECK();
+}
+
+template <typename O>
+static void restrict_o(hipStream_t st, Prec inner, const FieldPtr& r, const FieldPtr& rs, const FieldPtr& ps,
+                       const FieldPtr& t0, const void* E, const Lattice& lat, const SubTables& tc, int nsub, int Ls,
+                       double* partial) {
+  switch (inner) {
+    case Prec::F64: restrict_t<O, double>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
+    case Prec::F32: restrict_t<O, float>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
+    case Prec::F16: restrict_t<O, __half>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
+    case Prec::BF16: restrict_t<O, __hip_bfloat16>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
+  }
+}
+
+void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_outer, const FieldPtr& rs,
+                  const FieldPtr& ps, const FieldPtr& t0, const void* E, const Lattice& lat, const SubTables& tc,
+                  int nsub, int Ls, double* partial) {
+  if (outer == Prec::F64) restrict_o<double>(st, inner, r_outer, rs, ps, t0, E, lat, tc, nsub, Ls, partial);
+  else if (outer == Prec::F32) restrict_o<float>(st, inner, r_outer, rs, ps, t0, E, lat, tc, nsub, Ls, partial);
+  else throw std::runtime_error("sub_restrict: outer precision must be FP64 or FP32");
+}
+
+template <typename I>
+static void update_t(hipStream_t st, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& qs,
+                     const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls, double* partial) {
+  const int ns = c_ns(Ls, zs.prec);
+  hipLaunchKernelGGL((k_sub_update<I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)), 0,
+                     st, typed<I>(zs), typed<I>(ps), typed<I>(rs), typed<I>(qs), sc.alpha, first ? 1 : 0, tc, Ls, ns,
+                     partial);
+  LAUNCH_CHECK();
+}
+
+void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
+                const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
+                double* partial) {
+  switch (inner) {
+    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
+    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
+    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
+    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
+  }
+}
+
+template <typename I>
+static void xpay5_t(hipStream_t st, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0, const SubScalars& sc,
+                    const void* E, const SubTables& tc, int nsub, int Ls) {
+  using T = calc_t<I>;
+  const int ns = c_ns(Ls, ps.prec);
+  const size_t lds = 16 * sizeof(double) + sizeof(T) * (size_t)(2 * Ls * Ls + ns * tile_stride(Ls));
+  hipLaunchKernelGGL((k_sub_xpay5<I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)), lds,
+                     st, typed<I>(ps), typed<I>(rs), typed<I>(t0), sc.beta, (const T*)E, tc, Ls, ns);
+  LAUNCH_CHECK();
+}
+
+void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0,
+               const SubScalars& sc, const void* E, const SubTables& tc, int nsub, int Ls) {
+  switch (inner) {
+    case Prec::F64: xpay5_t<double>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
+    case Prec::F32: xpay5_t<float>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
+    case Prec::F16: xpay5_t<__half>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
+    case Prec::BF16: xpay5_t<__hip_bfloat16>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
+  }
+}
+
+template <typename O, typename I>
+static void prolong_t(hipStream_t st, const FieldPtr& z, const FieldPtr& zs, const FieldPtr& r, const FieldPtr* rold,
+                      const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* p1, double* p2) {
+  const int ns = c_ns(Ls, zs.prec);
+  Field<O> ro = rold ? typed<O>(*rold) : Field<O>{};
+  hipLaunchKernelGGL((k_sub_prolong<O, I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)),
+                     0, st, typed<O>(z), typed<I>(zs), typed<O>(r), ro, rold ? 1 : 0, lat, tc, Ls, ns, p1, p2);
+  LAUNCH_CHECK();
+}
+
+template <typename O>
+static void prolong_o(hipStream_t st, Prec inner, const FieldPtr& z, const FieldPtr& zs, const FieldPtr& r,
+                      const FieldPtr* rold, const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* p1,
+                      double* p2) {
+  switch (inner) {
+    case Prec::F64: prolong_t<O, double>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
+    case Prec::F32: prolong_t<O, float>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
+    case Prec::F16: prolong_t<O, __half>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
+    case Prec::BF16: prolong_t<O, __hip_bfloat16>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
+  }
+}
+
+void sub_prolong(hipStream_t st, Prec outer, Prec inner, const FieldPtr& z_outer, const FieldPtr& zs,
+                 const FieldPtr& r_outer, const FieldPtr* rold_outer, const Lattice& lat, const SubTables& tc,
+                 int nsub, int Ls, double* partial1, double* partial2) {
+  if (outer == Prec::F64) prolong_o<double>(st, inner, z_outer, zs, r_outer, rold_outer, lat, tc, nsub, Ls, partial1,
+                                            partial2);
+  else if (outer == Prec::F32) prolong_o<float>(st, inner, z_outer, zs, r_outer, rold_outer, lat, tc, nsub, Ls,
+                                                partial1, partial2);
+  else throw std::runtime_error("sub_prolong: outer precision must be FP64 or FP32");
+}
+
+void sub_finish(hipStream_t st, const double* partial, int bps, int nsub, const SubScalars& sc, int mode) {
+  hipLaunchKernelGGL(k_sub_finish, dim3((unsigned)((nsub + 255) / 256)), dim3(256), 0, st, partial, bps, nsub, sc.rho,
+                     sc.alpha, sc.beta, sc.active, mode);
+  LAUNCH_CHECK();
+}
+
+}  // namespace mspcg

@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+include/mspcg.h declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "mspcg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mspcg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2104_05615_amd as M
+    lib = ctypes.CDLL(M.LIB_PATH)
+    decl = header_functions()
+    assert len(decl) >= 12
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(decl) == sorted(M.EXPORTED)
+
+
+def test_create_validation_and_state_errors():
+    import paper_2104_05615_amd as M
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int32 * 4)(8, 8, 7, 8)
+    assert M.mspcg_create(ctypes.byref(h), bad, 0) == M.MSPCG_ERR_INVALID_ARG
+    assert "even" in M.mspcg_last_error().decode()
+    ok = (ctypes.c_int32 * 4)(8, 8, 8, 8)
+    assert M.mspcg_create(ctypes.byref(h), ok, -1) == M.MSPCG_ERR_INVALID_ARG
+    assert M.mspcg_create(ctypes.byref(h), ok, 0) == M.MSPCG_OK
+    try:
+        # tilings: validated before any device work
+        for sub, code in [((3, 4, 4, 4), M.MSPCG_ERR_BAD_TILING),     # odd
+                          ((6, 4, 4, 4), M.MSPCG_ERR_BAD_TILING),     # does not divide 8
+                          ((6, 8, 8, 8), M.MSPCG_ERR_BAD_TILING)]:
+            assert M.mspcg_set_subdomains(h, (ctypes.c_int32 * 4)(*sub)) == code
+        assert M.mspcg_set_mobius(h, 1, 1.5, 0.5, 1.8, 0.1) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_mobius(h, 40, 1.5, 0.5, 1.8, 0.1) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_mobius(h, 8, float("nan"), 0.5, 1.8, 0.1) == M.MSPCG_ERR_INVALID_ARG
+        # a singular M5: b (4 - M5) + 1 = 0
+        assert M.mspcg_set_mobius(h, 8, 1.0, 0.5, 5.0, 0.1) == M.MSPCG_ERR_INVALID_ARG
+        p = M.mspcg_solver_params(-1.0, 10, 4, 2, 1, 0.1, 0, 1)
+        assert M.mspcg_set_solver(h, ctypes.byref(p)) == M.MSPCG_ERR_INVALID_ARG
+        p = M.mspcg_solver_params(1e-10, 10, 4, 2, 2, 0.1, 0, 1)        # FP16 outer
+        assert M.mspcg_set_solver(h, ctypes.byref(p)) == M.MSPCG_ERR_INVALID_ARG
+        p = M.mspcg_solver_params(1e-10, 10, 4, 2, 1, 0.1, 3, 1)        # beta rule
+        assert M.mspcg_set_solver(h, ctypes.byref(p)) == M.MSPCG_ERR_INVALID_ARG
+        p = M.mspcg_solver_params(1e-10, 10, 4, 2, 1, 0.1, 0, 1)
+        assert M.mspcg_set_solver(h, ctypes.byref(p)) == M.MSPCG_OK
+        buf = (ctypes.c_double * 16)()
+        st = M.mspcg_stats()
+        assert M.mspcg_solve(h, buf, buf, None, ctypes.byref(st)) == M.MSPCG_ERR_NO_GAUGE
+        assert M.mspcg_apply(h, 99, 1, buf, buf) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_apply(h, 0, 7, buf, buf) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_apply(h, 0, 1, buf, buf) == M.MSPCG_ERR_NO_GAUGE
+        assert M.mspcg_solve(h, None, buf, None, None) == M.MSPCG_ERR_INVALID_ARG
+    finally:
+        assert M.mspcg_destroy(h) == M.MSPCG_OK
+    assert M.mspcg_destroy(None) == M.MSPCG_OK
+
+
+def test_python_wrapper_raises_on_error():
+    import paper_2104_05615_amd as M
+    s = M.MSPCG((8, 8, 8, 8), device=0)
+    with pytest.raises(M.MSPCGError) as e:
+        s.set_subdomains((4, 4, 4, 6))     # 6 does not divide 8
+    assert e.value.status == M.MSPCG_ERR_BAD_TILING
+    s.close()
+
+
+def test_tiling_rule_matches_oracle():
+    """Library and oracle accept exactly the same tilings (each checks its own copy of the rule)."""
+    import paper_2104_05615_amd as M
+    import oracle
+    dims = (8, 12, 16, 4)
+    s = M.MSPCG(dims, device=0)
+    try:
+        for sx in (2, 4, 6, 8):
+            for sy in (2, 4, 6, 12):
+                for sz in (4, 8, 16):
+                    for st in (2, 4):
+                        sub = (sx, sy, sz, st)
+                        want = oracle.tiling_ok(dims, sub)
+                        try:
+                            s.set_subdomains(sub)
+                            got = True
+                        except M.MSPCGError as e:
+                            # a valid tiling on a machine without a GPU fails later, at the device
+                            got = e.status != M.MSPCG_ERR_BAD_TILING
+                        assert got == want, sub
+    finally:
+        s.close()
