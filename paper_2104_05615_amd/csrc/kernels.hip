@@ -17,9 +17,12 @@ namespace mspcg {
   } while (0)
 
 int sites_per_block(int Ls, Prec p) {
-  // blocks of <= 256 threads; FP64 tiles kept small for occupancy
+  // blocks of <= 256 threads; FP64 tiles kept small for occupancy; the LDS
+  // of the widest site kernel (two tiles and three matrices) stays <= 60 KB
   int ns = 256 / Ls;
   if (p == Prec::F64 && ns > 8) ns = 8;
+  const size_t elem = p == Prec::F64 ? 8 : 4;
+  while (ns > 1 && 128 + elem * (size_t)(6 * Ls * Ls + 2 * ns * tile_stride(Ls)) > 60 * 1024) --ns;
   if (ns < 1) ns = 1;
   return ns;
 }
