@@ -1,0 +1,256 @@
+"""Benchmark: MSPCG vs CG time-to-solution on one MI355X.
+
+A step is one complete solve A x = b (A = D^dag D of the even-odd Mobius
+domain-wall operator) to a true relative residual of 1e-10, with the source
+and gauge field already resident in HBM.  The default workload is the single
+mixed-precision solve: 16^3x32 lattice, Ls = 12, mf = 0.01, links
+exp(i 0.5 H); outer PCG in FP32 with FP64 reliable updates, inner CG in FP16
+storage (FP32 arithmetic) on 256 subdomains of 4^3x8, 6 inner iterations.
+Plain CG (FP32 + FP64 reliable updates, and FP64) is timed beside it.
+
+Prints one JSON line.  `value` is the MSPCG time-to-solution in seconds.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MSPCG vs CG time-to-solution @ rel resid 1e-10; Dslash GB/s; p50/p99"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def region_counts(sub, dims):
+    """Sites of the subdomain centre C (even), its L1 distance-1 shell N1 (odd)
+    and distance-2 shell N2 (even), in the subdomain's local frame."""
+    part = [s < d for s, d in zip(sub, dims)]
+    rng = [range(-2, s + 2) if p else range(0, d) for s, d, p in zip(sub, dims, part)]
+    nC = nN1 = nN2 = 0
+    for t in rng[3]:
+        for z in rng[2]:
+            for y in rng[1]:
+                for x in rng[0]:
+                    c = (x, y, z, t)
+                    dist = sum(max(0, -c[m], c[m] - (sub[m] - 1)) for m in range(4) if part[m])
+                    par = (x + y + z + t) & 1
+                    nC += dist == 0 and par == 0
+                    nN1 += dist <= 1 and par == 1
+                    nN2 += dist <= 2 and par == 0
+    return nC, nN1, nN2
+
+
+def stage_bytes(cfg, inner_prec):
+    """Algorithmic bytes of one launch of each hop stage: every input site
+    read once, every output written once, the centre field read once where it
+    is nonzero, and the 8 FP32 links of each output 4D site read once (shared
+    over Ls).  Keys: profiling kinds of the library (21..24 outer FP32 hops of
+    A, 11..14 subdomain hops h1..h4)."""
+    X, Y, Z, T = cfg.dims
+    vh = X * Y * Z * T // 2
+    Ls = cfg.Ls
+    sp32 = 96
+    sp16 = {"fp16": 52, "bf16": 52, "fp32": 96, "fp64": 192}[inner_prec]
+    link = 8 * 18 * 4
+    n5 = vh * Ls
+    out = {21: 2 * sp32 * n5 + link * vh, 22: 3 * sp32 * n5 + link * vh,
+           23: 2 * sp32 * n5 + link * vh, 24: 3 * sp32 * n5 + link * vh}
+    nC, nN1, nN2 = region_counts(cfg.sub, cfg.dims)
+    ns = cfg.n_subdomains
+    for k, (sin, sout) in {11: (nC, nN1), 12: (nN1 + nC, nN2), 13: (nN2, nN1), 14: (nN1 + nC, nC)}.items():
+        out[k] = ns * (Ls * sp16 * (sin + sout) + link * sout)
+    return out, (nC, nN1, nN2)
+
+
+STAGE_NAMES = {
+    21: "k_hop<FullGeo,float,dag=0,w=0>: a = Q D^w_oe t0 (outer A, hop 1)",
+    22: "k_hop<FullGeo,float,dag=0,w=1>: c = M5^-dag(p - M5^-1 D^w_eo a) (outer A, hop 2)",
+    23: "k_hop<FullGeo,float,dag=1,w=0>: e = Q^dag D^w^dag_oe c (outer A, hop 3)",
+    24: "k_hop<FullGeo,float,dag=1,w=1>: q = M5^dag c - M_phi^dag D^w^dag_eo e (outer A, hop 4)",
+    11: "k_hop<SubGeo,half,dag=0,w=0>: h1 N1 <- C (inner A_s)",
+    12: "k_hop<SubGeo,half,dag=0,w=1>: h2 N2 <- N1 (inner A_s)",
+    13: "k_hop<SubGeo,half,dag=1,w=0>: h3 N1 <- N2 (inner A_s)",
+    14: "k_hop<SubGeo,half,dag=1,w=1>: h4 C <- N1 (inner A_s)",
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--inner-prec", default=None)
+    ap.add_argument("--cg-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus N > 1 is not supported"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from workloads.configs import CONFIGS
+    from paper_2104_05615_amd import MSPCG, KERNEL_INNER_HOP, KERNEL_OUTER_HOP, KERNEL_PRECOND
+
+    cfg = CONFIGS[args.config]
+    inner = args.inner_prec or cfg.inner_prec
+    log(f"[bench] workload {cfg.name}: {cfg.note}")
+    t0 = time.time()
+    U = W.gauge_field(cfg.dims, cfg.eps, cfg.gauge_seed)
+    b = W.gaussian_source(cfg.dims, cfg.Ls, cfg.src_seed)
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s")
+
+    s = MSPCG(cfg.dims, device=0)
+    s.load_gauge(U)
+    s.set_mobius(cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
+    s.set_subdomains(cfg.sub)
+    dev = torch.device("cuda:0")
+    bt = torch.from_numpy(b.view(np.float64).reshape(-1).copy()).to(dev)
+    xt = torch.empty_like(bt)
+    torch.cuda.synchronize()
+
+    def run(n, **solver):
+        s.set_solver(**solver)
+        out = []
+        for _ in range(n):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = s.solve_device(bt.data_ptr(), xt.data_ptr())
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t, st))
+        return out
+
+    mspcg_params = dict(tol=cfg.tol, maxiter=20000, inner_iters=cfg.inner_iters, inner_prec=inner,
+                        outer_prec=cfg.outer_prec, reliable_delta=0.1, beta_rule="PR", use_precond=True)
+    # warmup
+    for i in range(args.warmup):
+        (dt, st), = run(1, **mspcg_params)
+        log(f"[bench] warmup {i}: {dt:.3f}s, {st.outer_iters} outer iters, true resid {st.true_rel_resid:.2e}")
+    # timed region: K solves, per-kernel HIP events on the solver's stream
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    res = run(args.steps, **mspcg_params)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    n_out, ms_out = s.kernel_time(KERNEL_OUTER_HOP)
+    n_in, ms_in = s.kernel_time(KERNEL_INNER_HOP)
+    n_pc, ms_pc = s.kernel_time(KERNEL_PRECOND)
+    stage_t = {k: s.kernel_time(k) for k in STAGE_NAMES}
+    s.set_profiling(False)
+    times = [r[0] for r in res]
+    sts = [r[1] for r in res]
+    for i, (dt, st) in enumerate(res):
+        log(f"[bench] step {i}: {dt:.3f}s, {st.outer_iters} outer, {st.reliable_updates} RU, "
+            f"true resid {st.true_rel_resid:.2e}")
+    assert all(st.status == 0 and st.true_rel_resid <= cfg.tol for st in sts), "MSPCG did not converge"
+    x_ms = xt.clone()
+
+    # baselines on the same GPU (outside the timed region)
+    cg32 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp32", reliable_delta=0.1,
+               beta_rule="FR", use_precond=False)
+    log(f"[bench] CG fp32: {cg32[-1][0]:.3f}s, {cg32[-1][1].outer_iters} iters, "
+        f"true resid {cg32[-1][1].true_rel_resid:.2e}")
+    cg64 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp64", reliable_delta=0.1,
+               beta_rule="FR", use_precond=False)
+    log(f"[bench] CG fp64: {cg64[-1][0]:.3f}s, {cg64[-1][1].outer_iters} iters, "
+        f"true resid {cg64[-1][1].true_rel_resid:.2e}")
+    x_cg = xt.clone()
+    sol_rel = float(torch.linalg.vector_norm(x_ms - x_cg) / torch.linalg.vector_norm(x_cg))
+
+    # roofline of the hop kernels (HIP events over the timed region)
+    sbytes, regions = stage_bytes(cfg, inner)
+    kernels = {}
+    for k, (n, ms) in stage_t.items():
+        if n:
+            avg = ms / n
+            kernels[str(k)] = {"name": STAGE_NAMES[k], "launches": n, "total_ms": ms, "avg_ms": avg,
+                               "algorithmic_bytes": sbytes[k], "GBps": sbytes[k] / (avg * 1e-3) / 1e9}
+    dom = max(kernels.values(), key=lambda v: v["total_ms"])
+    roof = {"kernel": dom["name"], "bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": dom["avg_ms"],
+            "launches": dom["launches"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes"]}
+    outer_b = sum(sbytes[k] for k in (21, 22, 23, 24)) / 4
+    inner_b = sum(sbytes[k] for k in (11, 12, 13, 14)) / 4
+    avg_out = ms_out / max(n_out, 1)
+    avg_in = ms_in / max(n_in, 1)
+    gbs_out = outer_b / (avg_out * 1e-3) / 1e9 if n_out else None
+    gbs_in = inner_b / (avg_in * 1e-3) / 1e9 if n_in else None
+    ms_per_step = 1000.0 * total / args.steps
+    line = {
+        "metric": METRIC,
+        "value": ms_per_step / 1000.0,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.note}", "lattice": list(cfg.dims), "Ls": cfg.Ls,
+                   "mf": cfg.mf, "eps": cfg.eps, "subdomain": list(cfg.sub), "inner_iters": cfg.inner_iters,
+                   "inner_prec": inner, "outer_prec": cfg.outer_prec, "tol": cfg.tol,
+                   "parallelism": "single GPU, 256 virtual subdomains"},
+        "mspcg": {"time_s_median": statistics.median(times), "outer_iters": sts[-1].outer_iters,
+                  "inner_iters_total": sts[-1].inner_iters_total, "reliable_updates": sts[-1].reliable_updates,
+                  "true_rel_resid": sts[-1].true_rel_resid,
+                  "precond_ms_per_solve": ms_pc / args.steps},
+        "cg_fp32": {"time_s": cg32[-1][0], "outer_iters": cg32[-1][1].outer_iters,
+                    "true_rel_resid": cg32[-1][1].true_rel_resid},
+        "cg_fp64": {"time_s": cg64[-1][0], "outer_iters": cg64[-1][1].outer_iters,
+                    "true_rel_resid": cg64[-1][1].true_rel_resid},
+        "speedup_vs_cg_fp32": cg32[-1][0] / statistics.median(times),
+        "solution_rel_diff_mspcg_vs_cg64": sol_rel,
+        "kernels": kernels,
+        "dslash": {"outer_hop_GBps": gbs_out, "outer_hop_avg_ms": avg_out, "outer_launches": n_out,
+                   "inner_hop_GBps": gbs_in, "inner_hop_avg_ms": avg_in, "inner_launches": n_in,
+                   "outer_hop_ms_total": ms_out, "inner_hop_ms_total": ms_in, "regions_C_N1_N2": regions},
+        "roofline": roof,
+        "p50_p99": None,
+    }
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, U, b, sts[-1].outer_iters, cg32[-1][1].outer_iters)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(cfg, U, b, mspcg_iters, cg_iters):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    solve, scaled to a time-to-solution."""
+    os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+    import oracle
+    op = oracle.MobiusDWF(U, cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
+    til = oracle.Tiling(cfg.dims, cfg.sub)
+    t = time.perf_counter()
+    q = op.A(b)
+    t_A = time.perf_counter() - t
+    log(f"[bench] oracle: A in {t_A:.2f}s")
+    nsample = 1
+    t = time.perf_counter()
+    oracle.inner_cg(op, til, b, cfg.inner_iters, subset=[0])
+    t_pc1 = time.perf_counter() - t
+    log(f"[bench] oracle: inner CG (k={cfg.inner_iters}) on {nsample} subdomain in {t_pc1:.2f}s")
+    per_iter_ms = t_A + t_pc1 * til.nsub / nsample
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": per_iter_ms * mspcg_iters, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"one oracle A application ({t_A:.2f}s) and the inner CG on {nsample} of {til.nsub} "
+                       f"subdomains ({t_pc1:.2f}s), extrapolated to {til.nsub} subdomains and the GPU's "
+                       f"{mspcg_iters} outer iterations"),
+            "cg_fp64_extrapolated_s": t_A * cg_iters}
+
+
+if __name__ == "__main__":
+    main()

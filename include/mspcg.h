@@ -154,8 +154,11 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
 /* Kernel timing.  With profiling on, the library brackets every launch of its
  * hop kernels with HIP events on the stream they run on; mspcg_get_kernel_time
  * returns the number of timed launches and their summed duration in ms for a
- * kernel class: 0 = outer FP32/FP64 hop kernels, 1 = subdomain (inner) hop
- * kernels, 2 = preconditioner total.  Counters are reset by set_profiling(h, 1). */
+ * kernel class: 0 = full-lattice hop kernels in FP32/FP16/BF16, 1 = subdomain
+ * (inner) hop kernels, 2 = whole preconditioner applications, 3 = full-lattice
+ * hop kernels in FP64 (true residuals); or one hop stage of A: 21..24 (full
+ * lattice, FP32/16-bit), 31..34 (full lattice, FP64), 11..14 (subdomain hops
+ * h1..h4: N1<-C, N2<-N1, N1<-N2, C<-N1).  Counters are reset by set_profiling. */
 mspcg_status mspcg_set_profiling(mspcg_t h, int32_t on);
 mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, double* ms);
 

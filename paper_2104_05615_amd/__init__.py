@@ -51,7 +51,7 @@ OPS = {
     "m5": 4, "m5inv": 5, "mphi": 6, "D": 7, "Ddag": 8, "A": 9, "A_sub": 10, "precond": 11,
 }
 
-KERNEL_OUTER_HOP, KERNEL_INNER_HOP, KERNEL_PRECOND = 0, 1, 2
+KERNEL_OUTER_HOP, KERNEL_INNER_HOP, KERNEL_PRECOND, KERNEL_OUTER_HOP64 = 0, 1, 2, 3
 
 
 class mspcg_solver_params(ctypes.Structure):

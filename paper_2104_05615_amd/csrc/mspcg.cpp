@@ -403,13 +403,15 @@ struct mspcg_ctx {
   }
 
   // ---------------------------------------------------------------- operators
+  // stage: 1..4 for the four hops of A (0 for other uses); profiling kind
+  // 20 + stage (FP32/16-bit) or 30 + stage (FP64)
   void hop(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int out_par, bool dag,
-           const Epilogue& epi) {
+           const Epilogue& epi, int stage = 0) {
     HopGeometry g;
     g.lat = lat;
     g.out_parity = out_par;
     g.Ls = Ls;
-    const size_t e = ev_begin(st, 0);
+    const size_t e = ev_begin(st, (p == Prec::F64 ? 30 : 20) + stage);
     hop_full(st, p, out, in, w, gauge(p), g, dag, epi);
     ev_end(st, e);
   }
@@ -428,10 +430,10 @@ struct mspcg_ctx {
   void A_from_t0(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr& t0,
                  const std::string& tag, double* norm_partial) {
     FieldPtr a = field(tag + ".a", p, lat.vh), c = field(tag + ".c", p, lat.vh), e = field(tag + ".e", p, lat.vh);
-    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q, -1));
-    hop(st, p, c, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, MAT_M5INV_T, true, norm_partial));
-    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT, -1));
-    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, -1));
+    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q, -1), 1);
+    hop(st, p, c, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, MAT_M5INV_T, true, norm_partial), 2);
+    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT, -1), 3);
+    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, -1), 4);
   }
 
   void A_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag,
@@ -462,7 +464,7 @@ struct mspcg_ctx {
              e = field("in.e", I, (int64_t)nsub * nN1);
     auto run = [&](int which, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int par, bool dag,
                    const Epilogue& E) {
-      const size_t ev = ev_begin(st, 1);
+      const size_t ev = ev_begin(st, 10 + which);
       hop_sub(st, I, out, in, w, gauge(I), lat, par, tables(which, I), nsub, Ls, dag, E);
       ev_end(st, ev);
     };
@@ -972,8 +974,16 @@ mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, d
     *ms = 0;
     if (!h->hip_ready) return MSPCG_OK;
     HIPCHK(hipDeviceSynchronize());
+    auto match = [kind](int k) {
+      switch (kind) {
+        case 0: return k >= 20 && k < 30;
+        case 1: return k >= 10 && k < 20;
+        case 3: return k >= 30 && k < 40;
+        default: return k == kind;
+      }
+    };
     for (auto& kv : h->ev_log) {
-      if (kv.first != kind) continue;
+      if (!match(kv.first)) continue;
       float m = 0;
       HIPCHK(hipEventElapsedTime(&m, h->ev_pool[kv.second].a, h->ev_pool[kv.second].b));
       *ms += m;
