@@ -87,36 +87,85 @@ template <> __device__ __forceinline__ uint4 pack8<__hip_bfloat16>(const float* 
   return c;
 }
 
+// Site access through raw buffer instructions: one 128-bit resource per
+// field (scalar registers), the site's byte offset in one vector register
+// shared by all chunks, and each chunk array's offset as a scalar.  A field
+// must be smaller than 4 GiB (checked on the host).  Accesses past the
+// resource's range read zero and drop stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kBufferConfig = 0x00020000;   // raw buffer, 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)(uint32_t)bytes, kBufferConfig);
+}
+
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const Field<S>& f) {
+  using C = typename Field<S>::chunk;
+  return make_rsrc(f.data, (uint64_t)StoreTraits<S>::nchunk * (uint64_t)f.stride * sizeof(C));
+}
+
 template <typename S, typename T>
-__device__ __forceinline__ void load_site(const Field<S>& f, int64_t i, T* v) {
+__device__ __forceinline__ void load_site(const Field<S>& f, uint32_t i, T* v) {
+  using C = typename Field<S>::chunk;
+  const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+  const uint32_t off = i * (uint32_t)sizeof(C);
+  const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
   if constexpr (sizeof(S) == 8) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) { double2 c = f.data[k * f.stride + i]; v[2 * k] = c.x; v[2 * k + 1] = c.y; }
+    for (int k = 0; k < 12; ++k) {
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      v[2 * k] = __hiloint2double(c.y, c.x);
+      v[2 * k + 1] = __hiloint2double(c.w, c.z);
+    }
   } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 c = f.data[k * f.stride + i];
-      v[4 * k] = c.x; v[4 * k + 1] = c.y; v[4 * k + 2] = c.z; v[4 * k + 3] = c.w;
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      v[4 * k] = __uint_as_float(c.x); v[4 * k + 1] = __uint_as_float(c.y);
+      v[4 * k + 2] = __uint_as_float(c.z); v[4 * k + 3] = __uint_as_float(c.w);
     }
   } else {
-    const float sc = f.scale[i];
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+    const float sc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
     float tmp[24];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) unpack8<S>(f.data[k * f.stride + i], tmp + 8 * k);
+    for (int k = 0; k < 3; ++k) {
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      uint4 q;
+      q.x = c.x; q.y = c.y; q.z = c.z; q.w = c.w;
+      unpack8<S>(q, tmp + 8 * k);
+    }
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = tmp[k] * sc;
   }
 }
 
 template <typename S, typename T>
-__device__ __forceinline__ void store_site(const Field<S>& f, int64_t i, const T* v) {
+__device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const T* v) {
+  using C = typename Field<S>::chunk;
+  const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+  const uint32_t off = i * (uint32_t)sizeof(C);
+  const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
   if constexpr (sizeof(S) == 8) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) f.data[k * f.stride + i] = make_double2(v[2 * k], v[2 * k + 1]);
+    for (int k = 0; k < 12; ++k) {
+      u32x4 c;
+      const double a = (double)v[2 * k], b = (double)v[2 * k + 1];
+      c.x = (uint32_t)__double2loint(a); c.y = (uint32_t)__double2hiint(a);
+      c.z = (uint32_t)__double2loint(b); c.w = (uint32_t)__double2hiint(b);
+      __builtin_amdgcn_raw_buffer_store_b128(c, r, off, k * cs, 0);
+    }
   } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-      f.data[k * f.stride + i] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    for (int k = 0; k < 6; ++k) {
+      u32x4 c;
+      c.x = __float_as_uint((float)v[4 * k]); c.y = __float_as_uint((float)v[4 * k + 1]);
+      c.z = __float_as_uint((float)v[4 * k + 2]); c.w = __float_as_uint((float)v[4 * k + 3]);
+      __builtin_amdgcn_raw_buffer_store_b128(c, r, off, k * cs, 0);
+    }
   } else {
     float mx = 0.f;
 #pragma unroll
@@ -126,8 +175,14 @@ __device__ __forceinline__ void store_site(const Field<S>& f, int64_t i, const T
 #pragma unroll
     for (int k = 0; k < 24; ++k) tmp[k] = (float)v[k] * inv;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f.data[k * f.stride + i] = pack8<S>(tmp + 8 * k);
-    f.scale[i] = mx;
+    for (int k = 0; k < 3; ++k) {
+      const uint4 q = pack8<S>(tmp + 8 * k);
+      u32x4 c;
+      c.x = q.x; c.y = q.y; c.z = q.z; c.w = q.w;
+      __builtin_amdgcn_raw_buffer_store_b128(c, r, off, k * cs, 0);
+    }
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(mx), rs, i * 4u, 0, 0);
   }
 }
 
@@ -139,16 +194,27 @@ template <typename L> struct Gauge {
   using c2 = typename std::conditional<sizeof(L) == 8, double2, float2>::type;
   const c2* data;
   int64_t vh;
-  __device__ __forceinline__ const c2* link(int parity, int mu, int64_t site) const {
-    return data + ((int64_t)(parity * 4 + mu) * 9) * vh + site;
-  }
 };
 
 template <typename L, typename T>
-__device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu, int64_t site, T* u) {
-  const auto* p = g.link(parity, mu, site);
+__device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu, uint32_t site, T* u) {
+  using C2 = typename Gauge<L>::c2;
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(g.data, (uint64_t)72 * (uint64_t)g.vh * sizeof(C2));
+  const uint32_t ks = (uint32_t)g.vh * (uint32_t)sizeof(C2);
+  const uint32_t base = (uint32_t)((parity * 4 + mu) * 9) * ks;
+  const uint32_t off = site * (uint32_t)sizeof(C2);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) { auto c = p[k * g.vh]; u[2 * k] = (T)c.x; u[2 * k + 1] = (T)c.y; }
+  for (int k = 0; k < 9; ++k) {
+    if constexpr (sizeof(C2) == 16) {
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, base + k * ks, 0);
+      u[2 * k] = (T)__hiloint2double(c.y, c.x);
+      u[2 * k + 1] = (T)__hiloint2double(c.w, c.z);
+    } else {
+      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(r, off, base + k * ks, 0);
+      u[2 * k] = (T)__uint_as_float(c.x);
+      u[2 * k + 1] = (T)__uint_as_float(c.y);
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -215,7 +281,11 @@ __device__ __forceinline__ void reconstruct_add(const T* g, T* acc) {
   }
 }
 
-// g = U h (DAG = false) or U^dag h (DAG = true), for the two spins of h
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// g = U h (DAG = false) or U^dag h (DAG = true), for the two spins of h;
+// every complex product-accumulate is four fused multiply-adds
 template <bool DAG, typename T>
 __device__ __forceinline__ void su3_mul_half(const T* u, const T* h, T* g) {
 #pragma unroll
@@ -228,8 +298,10 @@ __device__ __forceinline__ void su3_mul_half(const T* u, const T* h, T* g) {
         const int k = DAG ? (b * 3 + a) : (a * 3 + b);
         const T ur = u[2 * k], ui = DAG ? -u[2 * k + 1] : u[2 * k + 1];
         const T hr = h[(sp * 3 + b) * 2], hi = h[(sp * 3 + b) * 2 + 1];
-        re += ur * hr - ui * hi;
-        im += ur * hi + ui * hr;
+        re = fmadd(ur, hr, re);
+        re = fmadd(-ui, hi, re);
+        im = fmadd(ur, hi, im);
+        im = fmadd(ui, hr, im);
       }
       g[(sp * 3 + a) * 2] = re;
       g[(sp * 3 + a) * 2 + 1] = im;
@@ -252,24 +324,58 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
 // --------------------------------------------------------------------------
 // lattice geometry of one parity (single-parity index = lex / 2)
 // --------------------------------------------------------------------------
+// n / d for 0 <= n < 2^31 by multiply-high: s = ceil(log2 d),
+// m = ceil(2^(32+s) / d) - 2^32, n / d = (mulhi(n, m) + n) >> s.
+struct FastDiv {
+  uint32_t d, m, s;
+  __device__ __forceinline__ uint32_t div(uint32_t n) const { return (__umulhi(n, m) + n) >> s; }
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)((((1ull << (32 + s)) + d - 1) / d) - (1ull << 32));
+  return f;
+}
+
 struct Lattice {
   int X, Y, Z, T;
   int64_t vh;
+  FastDiv fx, fy, fz;   // division by X, Y, Z
+
   __device__ __forceinline__ void coords(int64_t i, int parity, int* c) const {
-    const int64_t l0 = 2 * i;
-    const int x0 = (int)(l0 % X);
-    const int64_t r = l0 / X;
-    c[1] = (int)(r % Y);
-    const int64_t r2 = r / Y;
-    c[2] = (int)(r2 % Z);
-    c[3] = (int)(r2 / Z);
+    const uint32_t l0 = 2u * (uint32_t)i;
+    const uint32_t q1 = fx.div(l0);
+    const int x0 = (int)(l0 - q1 * (uint32_t)X);
+    const uint32_t q2 = fy.div(q1);
+    c[1] = (int)(q1 - q2 * (uint32_t)Y);
+    const uint32_t q3 = fz.div(q2);
+    c[2] = (int)(q2 - q3 * (uint32_t)Z);
+    c[3] = (int)q3;
     c[0] = x0 + ((c[1] + c[2] + c[3] + parity) & 1);
   }
-  __device__ __forceinline__ int64_t index(const int* c) const {
-    return ((int64_t)c[0] + (int64_t)X * ((int64_t)c[1] + (int64_t)Y * ((int64_t)c[2] + (int64_t)Z * c[3]))) >> 1;
+  __device__ __forceinline__ uint32_t lex(const int* c) const {
+    return (uint32_t)c[0] + (uint32_t)X * ((uint32_t)c[1] + (uint32_t)Y * ((uint32_t)c[2] + (uint32_t)Z * (uint32_t)c[3]));
   }
+  __device__ __forceinline__ uint32_t index(const int* c) const { return lex(c) >> 1; }
   __device__ __forceinline__ int ext(int mu) const { return mu == 0 ? X : mu == 1 ? Y : mu == 2 ? Z : T; }
+  __device__ __forceinline__ uint32_t stride(int mu) const {
+    return mu == 0 ? 1u : mu == 1 ? (uint32_t)X : mu == 2 ? (uint32_t)X * Y : (uint32_t)X * Y * Z;
+  }
 };
+
+inline Lattice make_lattice(int X, int Y, int Z, int T) {
+  Lattice l;
+  l.X = X; l.Y = Y; l.Z = Z; l.T = T;
+  l.vh = (int64_t)X * Y * Z * T / 2;
+  l.fx = make_fastdiv(X);
+  l.fy = make_fastdiv(Y);
+  l.fz = make_fastdiv(Z);
+  return l;
+}
 
 // --------------------------------------------------------------------------
 // subdomain region tables
@@ -282,6 +388,7 @@ struct Lattice {
 // (dir 0: +mu, 1: -mu) in the input region of the hop, or -1 if the input
 // vanishes there (outside the region: zero Dirichlet pad).
 struct SubTables {
+  const short4* origin;   // [nsub] global coordinates of each subdomain's corner
   const short4* coords;   // [n_out] local coordinates of the output sites
   const int* nbr;         // [n_out][8]
   const int* wmap;        // [n_out] index into the centre-field region, -1 = zero; null = same region

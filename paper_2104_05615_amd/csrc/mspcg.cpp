@@ -265,7 +265,7 @@ struct mspcg_ctx {
   bool have_tiling = false;
   int nsub = 0, nblk[4] = {1, 1, 1, 1};
   int nC = 0, nN1 = 0, nN2 = 0;
-  DevBuf tb_cC, tb_cN1, tb_cN2, tb_nbr1, tb_nbr2, tb_nbr3, tb_nbr4, tb_w2, tb_w4;
+  DevBuf tb_origin, tb_cC, tb_cN1, tb_cN2, tb_nbr1, tb_nbr2, tb_nbr3, tb_nbr4, tb_w2, tb_w4;
 
   mspcg_solver_params sp;
   bool have_solver = false;
@@ -281,11 +281,7 @@ struct mspcg_ctx {
   mspcg_ctx(const int32_t* d, int dev) {
     for (int m = 0; m < 4; ++m) dims[m] = d[m];
     device = dev;
-    lat.X = d[0];
-    lat.Y = d[1];
-    lat.Z = d[2];
-    lat.T = d[3];
-    lat.vh = (int64_t)d[0] * d[1] * d[2] * d[3] / 2;
+    lat = make_lattice(d[0], d[1], d[2], d[3]);
     sp.tol = 1e-10;
     sp.maxiter = 10000;
     sp.inner_iters = 6;
@@ -381,6 +377,7 @@ struct mspcg_ctx {
       t.nblk[m] = nblk[m];
     }
     const int ns = sites_per_block(Ls, p);
+    t.origin = tb_origin.as<short4>();
     switch (which) {
       case 0:   // C (restrict / update / prolong)
         t.coords = tb_cC.as<short4>(); t.nbr = nullptr; t.wmap = nullptr;
@@ -862,6 +859,15 @@ mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
     up(h->tb_nbr4, H.nbr4.data(), H.nbr4.size() * sizeof(int));
     up(h->tb_w2, H.wmap2.data(), H.wmap2.size() * sizeof(int));
     up(h->tb_w4, H.wmap4.data(), H.wmap4.size() * sizeof(int));
+    std::vector<short4> origin;
+    int nb[4];
+    for (int m = 0; m < 4; ++m) nb[m] = h->dims[m] / s[m];
+    for (int d3 = 0; d3 < nb[3]; ++d3)
+      for (int d2 = 0; d2 < nb[2]; ++d2)
+        for (int d1 = 0; d1 < nb[1]; ++d1)
+          for (int d0 = 0; d0 < nb[0]; ++d0)
+            origin.push_back(make_short4((short)(d0 * s[0]), (short)(d1 * s[1]), (short)(d2 * s[2]), (short)(d3 * s[3])));
+    up(h->tb_origin, origin.data(), origin.size() * sizeof(short4));
     h->nC = (int)H.C.coords.size();
     h->nN1 = (int)H.N1.coords.size();
     h->nN2 = (int)H.N2.coords.size();

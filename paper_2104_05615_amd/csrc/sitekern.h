@@ -46,25 +46,26 @@ template <typename T> struct FullGeo {
     return r;
   }
 
+  // neighbours along mu differ in lex by the stride of mu (periodic wrap)
   template <int MU, bool DAG, typename S>
-  __device__ __forceinline__ void dir(const Field<S>& in, const int* c, int64_t site, int s, int Ls, T* acc) const {
+  __device__ __forceinline__ void dir(const Field<S>& in, const int* c, uint32_t lx, uint32_t site, int s, int Ls,
+                                      T* acc) const {
     constexpr int SF = DAG ? +1 : -1;  // (1 - gamma) forward, (1 + gamma) backward; flipped for the adjoint
     constexpr int SB = -SF;
-    int n[4] = {c[0], c[1], c[2], c[3]};
     const int L = lat.ext(MU);
+    const uint32_t st = lat.stride(MU);
+    const uint32_t lf = (c[MU] + 1 == L) ? lx - (uint32_t)(L - 1) * st : lx + st;
+    const uint32_t lb = (c[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
+    const uint32_t jf = lf >> 1, jb = lb >> 1;
     T psi[24], h[12], gh[12], u[18];
-    n[MU] = (c[MU] + 1 == L) ? 0 : c[MU] + 1;
-    int64_t j = lat.index(n);
-    load_site(in, j * Ls + s, psi);
+    load_site(in, jf * (uint32_t)Ls + (uint32_t)s, psi);
     project<MU, SF>(psi, h);
     load_link(g, par, MU, site, u);
     su3_mul_half<false>(u, h, gh);
     reconstruct_add<MU, SF>(gh, acc);
-    n[MU] = (c[MU] == 0) ? L - 1 : c[MU] - 1;
-    j = lat.index(n);
-    load_site(in, j * Ls + s, psi);
+    load_site(in, jb * (uint32_t)Ls + (uint32_t)s, psi);
     project<MU, SB>(psi, h);
-    load_link(g, 1 - par, MU, j, u);
+    load_link(g, 1 - par, MU, jb, u);
     su3_mul_half<true>(u, h, gh);
     reconstruct_add<MU, SB>(gh, acc);
   }
@@ -73,12 +74,14 @@ template <typename T> struct FullGeo {
   __device__ __forceinline__ void hop(const Field<S>& in, const SiteRef& r, int s, int Ls, T* acc) const {
     int c[4];
     lat.coords(r.site, par, c);
+    const uint32_t lx = lat.lex(c);
+    const uint32_t site = (uint32_t)r.site;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
-    dir<0, DAG>(in, c, r.site, s, Ls, acc);
-    dir<1, DAG>(in, c, r.site, s, Ls, acc);
-    dir<2, DAG>(in, c, r.site, s, Ls, acc);
-    dir<3, DAG>(in, c, r.site, s, Ls, acc);
+    dir<0, DAG>(in, c, lx, site, s, Ls, acc);
+    dir<1, DAG>(in, c, lx, site, s, Ls, acc);
+    dir<2, DAG>(in, c, lx, site, s, Ls, acc);
+    dir<3, DAG>(in, c, lx, site, s, Ls, acc);
   }
 };
 
@@ -106,43 +109,27 @@ template <typename T> struct SubGeo {
     return r;
   }
 
-  __device__ __forceinline__ void global_coords(int64_t d, const short4& lc, int* gco) const {
-    int64_t q = d;
-    const int b0 = (int)(q % tb.nblk[0]); q /= tb.nblk[0];
-    const int b1 = (int)(q % tb.nblk[1]); q /= tb.nblk[1];
-    const int b2 = (int)(q % tb.nblk[2]); q /= tb.nblk[2];
-    const int b3 = (int)q;
-    const int l[4] = {lc.x, lc.y, lc.z, lc.w};
-    const int b[4] = {b0, b1, b2, b3};
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      int v = b[m] * tb.sub[m] + l[m];
-      if (v < 0) v += tb.dims[m];
-      if (v >= tb.dims[m]) v -= tb.dims[m];
-      gco[m] = v;
-    }
-  }
-
   template <int MU, bool DAG, typename S>
-  __device__ __forceinline__ void dir(const Field<S>& in, const SiteRef& r, const int* gco, const int* nb, int s,
-                                      int Ls, T* acc) const {
+  __device__ __forceinline__ void dir(const Field<S>& in, uint32_t base_in, const int* gco, uint32_t lx,
+                                      const int* nb, int s, int Ls, T* acc) const {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     T psi[24], h[12], gh[12], u[18];
     const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
     if (jf >= 0) {
-      load_site(in, (r.d * tb.n_in + jf) * Ls + s, psi);
+      load_site(in, (base_in + (uint32_t)jf) * (uint32_t)Ls + (uint32_t)s, psi);
       project<MU, SF>(psi, h);
-      load_link(g, par, MU, lat.index(gco), u);
+      load_link(g, par, MU, lx >> 1, u);
       su3_mul_half<false>(u, h, gh);
       reconstruct_add<MU, SF>(gh, acc);
     }
     if (jb >= 0) {
-      int n[4] = {gco[0], gco[1], gco[2], gco[3]};
-      n[MU] = (gco[MU] == 0) ? lat.ext(MU) - 1 : gco[MU] - 1;
-      load_site(in, (r.d * tb.n_in + jb) * Ls + s, psi);
+      const int L = lat.ext(MU);
+      const uint32_t st = lat.stride(MU);
+      const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
+      load_site(in, (base_in + (uint32_t)jb) * (uint32_t)Ls + (uint32_t)s, psi);
       project<MU, SB>(psi, h);
-      load_link(g, 1 - par, MU, lat.index(n), u);
+      load_link(g, 1 - par, MU, lb >> 1, u);
       su3_mul_half<true>(u, h, gh);
       reconstruct_add<MU, SB>(gh, acc);
     }
@@ -152,15 +139,26 @@ template <typename T> struct SubGeo {
   __device__ __forceinline__ void hop(const Field<S>& in, const SiteRef& r, int s, int Ls, T* acc) const {
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
+    const short4 o = tb.origin[r.d];          // uniform over the block
+    const short4 lc = tb.coords[r.site];
+    const int l[4] = {o.x + lc.x, o.y + lc.y, o.z + lc.z, o.w + lc.w};
     int gco[4];
-    global_coords(r.d, tb.coords[r.site], gco);
-    int nb[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) nb[k] = tb.nbr[r.site * 8 + k];
-    dir<0, DAG>(in, r, gco, nb, s, Ls, acc);
-    dir<1, DAG>(in, r, gco, nb, s, Ls, acc);
-    dir<2, DAG>(in, r, gco, nb, s, Ls, acc);
-    dir<3, DAG>(in, r, gco, nb, s, Ls, acc);
+    for (int m = 0; m < 4; ++m) {
+      int v = l[m];
+      if (v < 0) v += tb.dims[m];
+      if (v >= tb.dims[m]) v -= tb.dims[m];
+      gco[m] = v;
+    }
+    const uint32_t lx = lat.lex(gco);
+    const int4 n0 = reinterpret_cast<const int4*>(tb.nbr)[2 * r.site];
+    const int4 n1 = reinterpret_cast<const int4*>(tb.nbr)[2 * r.site + 1];
+    const int nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+    const uint32_t base_in = (uint32_t)r.d * (uint32_t)tb.n_in;
+    dir<0, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
+    dir<1, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
+    dir<2, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
+    dir<3, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
   }
 };
 
@@ -279,12 +277,12 @@ k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, int Ls, int ns, const calc
     }
   }
   if (norm_partial) {
-    double loc = 0;
+    T loc = 0;
     if (valid) {
 #pragma unroll
-      for (int k = 0; k < 24; ++k) loc += (double)y[k] * (double)y[k];
+      for (int k = 0; k < 24; ++k) loc += y[k] * y[k];
     }
-    const double tot = block_sum(loc, red);
+    const double tot = block_sum((double)loc, red);
     if (tid == 0) norm_partial[blk] = tot;
   }
   if (E2) {

@@ -42,15 +42,11 @@ __device__ __forceinline__ CSite c_site(const SubTables& tc, int ns, int Ls) {
 }
 
 // global single-parity index of centre site j of subdomain d
-__device__ __forceinline__ int64_t c_global(const SubTables& tc, const Lattice& lat, int64_t d, int64_t j) {
+__device__ __forceinline__ uint32_t c_global(const SubTables& tc, const Lattice& lat, int64_t d, int64_t j) {
+  const short4 o = tc.origin[d];
   const short4 lc = tc.coords[j];
-  int64_t q = d;
-  const int b0 = (int)(q % tc.nblk[0]); q /= tc.nblk[0];
-  const int b1 = (int)(q % tc.nblk[1]); q /= tc.nblk[1];
-  const int b2 = (int)(q % tc.nblk[2]); q /= tc.nblk[2];
-  const int b3 = (int)q;
   // centre sites lie inside the subdomain: no wrap needed
-  int g[4] = {b0 * tc.sub[0] + lc.x, b1 * tc.sub[1] + lc.y, b2 * tc.sub[2] + lc.z, b3 * tc.sub[3] + lc.w};
+  const int g[4] = {o.x + lc.x, o.y + lc.y, o.z + lc.z, o.w + lc.w};
   return lat.index(g);
 }
 
@@ -184,12 +180,17 @@ k_sub_prolong(Field<O> z, Field<I> zs, Field<O> r, Field<O> rold, int has_rold, 
   }
 }
 
-__global__ void k_sub_finish(const double* partial, int bps, int nsub, double* rho, double* alpha, double* beta,
-                             int* active, int mode) {
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= nsub) return;
+// one wavefront per subdomain: lane l sums partials l, l+64, ... in order,
+// then a fixed butterfly over the 64 lanes -- deterministic
+__global__ void __launch_bounds__(64)
+k_sub_finish(const double* partial, int bps, int nsub, double* rho, double* alpha, double* beta, int* active,
+             int mode) {
+  const int d = blockIdx.x;
+  const int lane = threadIdx.x;
   double S = 0;
-  for (int b = 0; b < bps; ++b) S += partial[(int64_t)d * bps + b];
+  for (int b = lane; b < bps; b += 64) S += partial[(int64_t)d * bps + b];
+  for (int off = 32; off > 0; off >>= 1) S += __shfl_xor(S, off);
+  if (lane != 0 || d >= nsub) return;
   switch (mode) {
     case SUB_INIT:
       rho[d] = S;
@@ -319,7 +320,7 @@ void sub_prolong(hipStream_t st, Prec outer, Prec inner, const FieldPtr& z_outer
 }
 
 void sub_finish(hipStream_t st, const double* partial, int bps, int nsub, const SubScalars& sc, int mode) {
-  hipLaunchKernelGGL(k_sub_finish, dim3((unsigned)((nsub + 255) / 256)), dim3(256), 0, st, partial, bps, nsub, sc.rho,
+  hipLaunchKernelGGL(k_sub_finish, dim3((unsigned)nsub), dim3(64), 0, st, partial, bps, nsub, sc.rho,
                      sc.alpha, sc.beta, sc.active, mode);
   LAUNCH_CHECK();
 }
