@@ -51,10 +51,11 @@ def region_counts(sub, dims):
 
 def stage_bytes(cfg, inner_prec):
     """Algorithmic bytes of one launch of each hop stage: every input site
-    read once, every output written once, the centre field read once where it
-    is nonzero, and the 8 FP32 links of each output 4D site read once (shared
-    over Ls).  Keys: profiling kinds of the library (21..24 outer FP32 hops of
-    A, 11..14 subdomain hops h1..h4)."""
+    read once, every output written once, the epilogue's second field (w) and,
+    in the last hop, the field of the fused <p, A p> partial read once where
+    they are nonzero, and the 8 FP32 links of each output 4D site read once
+    (shared over Ls).  Keys: profiling kinds of the library (21..24 outer FP32
+    hops of A, 11..14 subdomain hops h1..h4)."""
     X, Y, Z, T = cfg.dims
     vh = X * Y * Z * T // 2
     Ls = cfg.Ls
@@ -63,10 +64,10 @@ def stage_bytes(cfg, inner_prec):
     link = 8 * 18 * 4
     n5 = vh * Ls
     out = {21: 2 * sp32 * n5 + link * vh, 22: 3 * sp32 * n5 + link * vh,
-           23: 2 * sp32 * n5 + link * vh, 24: 3 * sp32 * n5 + link * vh}
+           23: 2 * sp32 * n5 + link * vh, 24: 4 * sp32 * n5 + link * vh}
     nC, nN1, nN2 = region_counts(cfg.sub, cfg.dims)
     ns = cfg.n_subdomains
-    for k, (sin, sout) in {11: (nC, nN1), 12: (nN1 + nC, nN2), 13: (nN2, nN1), 14: (nN1 + nC, nC)}.items():
+    for k, (sin, sout) in {11: (nC, nN1), 12: (nN1 + nC, nN2), 13: (nN2, nN1), 14: (nN1 + 2 * nC, nC)}.items():
         out[k] = ns * (Ls * sp16 * (sin + sout) + link * sout)
     return out, (nC, nN1, nN2)
 
@@ -75,11 +76,11 @@ STAGE_NAMES = {
     21: "k_hop<FullGeo,float,dag=0,w=0>: a = Q D^w_oe t0 (outer A, hop 1)",
     22: "k_hop<FullGeo,float,dag=0,w=1>: c = M5^-dag(p - M5^-1 D^w_eo a) (outer A, hop 2)",
     23: "k_hop<FullGeo,float,dag=1,w=0>: e = Q^dag D^w^dag_oe c (outer A, hop 3)",
-    24: "k_hop<FullGeo,float,dag=1,w=1>: q = M5^dag c - M_phi^dag D^w^dag_eo e (outer A, hop 4)",
+    24: "k_hop<FullGeo,float,dag=1,w=1>: q = M5^dag c - M_phi^dag D^w^dag_eo e, <p,q> (outer A, hop 4)",
     11: "k_hop<SubGeo,half,dag=0,w=0>: h1 N1 <- C (inner A_s)",
     12: "k_hop<SubGeo,half,dag=0,w=1>: h2 N2 <- N1 (inner A_s)",
     13: "k_hop<SubGeo,half,dag=1,w=0>: h3 N1 <- N2 (inner A_s)",
-    14: "k_hop<SubGeo,half,dag=1,w=1>: h4 C <- N1 (inner A_s)",
+    14: "k_hop<SubGeo,half,dag=1,w=1>: h4 C <- N1, <p_s,q_s> (inner A_s)",
 }
 
 

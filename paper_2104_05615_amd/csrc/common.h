@@ -25,8 +25,6 @@ namespace mspcg {
 // Chirality: spins 0,1 (components 0..11) are P+, spins 2,3 are P-.
 // --------------------------------------------------------------------------
 
-struct half8 { __half2 h[4]; };
-struct bf16x8 { __hip_bfloat162 h[4]; };
 
 template <typename S> struct StoreTraits;
 template <> struct StoreTraits<double> {
@@ -49,18 +47,29 @@ template <typename S> struct Field {
   int64_t stride;
 };
 
+// 16-bit values are taken from and put into 32-bit words with shifts only:
+// no pointer type punning between the vector word types and __half.
+__device__ __forceinline__ uint32_t word(const uint4& c, int j) {
+  return j == 0 ? c.x : j == 1 ? c.y : j == 2 ? c.z : c.w;
+}
+__device__ __forceinline__ float half_lo(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
+__device__ __forceinline__ float half_hi(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
+
 template <typename S> __device__ __forceinline__ void unpack8(const uint4& c, float* v);
 template <> __device__ __forceinline__ void unpack8<__half>(const uint4& c, float* v) {
-  const __half2* h = reinterpret_cast<const __half2*>(&c);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) { float2 f = __half22float2(h[j]); v[2 * j] = f.x; v[2 * j + 1] = f.y; }
-}
-template <> __device__ __forceinline__ void unpack8<__hip_bfloat16>(const uint4& c, float* v) {
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(&c);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    v[2 * j] = __uint_as_float(w[j] << 16);
-    v[2 * j + 1] = __uint_as_float(w[j] & 0xffff0000u);
+    const uint32_t w = word(c, j);
+    v[2 * j] = half_lo(w);
+    v[2 * j + 1] = half_hi(w);
+  }
+}
+template <> __device__ __forceinline__ void unpack8<__hip_bfloat16>(const uint4& c, float* v) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t w = word(c, j);
+    v[2 * j] = __uint_as_float(w << 16);
+    v[2 * j + 1] = __uint_as_float(w & 0xffff0000u);
   }
 }
 
@@ -71,19 +80,23 @@ __device__ __forceinline__ uint32_t f2bf_rne(float f) {
   return u >> 16;
 }
 
+__device__ __forceinline__ uint32_t f2h_bits(float f) { return (uint32_t)__half_as_ushort(__float2half_rn(f)); }
+
 template <typename S> __device__ __forceinline__ uint4 pack8(const float* v);
 template <> __device__ __forceinline__ uint4 pack8<__half>(const float* v) {
   uint4 c;
-  __half2* h = reinterpret_cast<__half2*>(&c);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) h[j] = __floats2half2_rn(v[2 * j], v[2 * j + 1]);
+  c.x = f2h_bits(v[0]) | (f2h_bits(v[1]) << 16);
+  c.y = f2h_bits(v[2]) | (f2h_bits(v[3]) << 16);
+  c.z = f2h_bits(v[4]) | (f2h_bits(v[5]) << 16);
+  c.w = f2h_bits(v[6]) | (f2h_bits(v[7]) << 16);
   return c;
 }
 template <> __device__ __forceinline__ uint4 pack8<__hip_bfloat16>(const float* v) {
   uint4 c;
-  uint32_t* w = reinterpret_cast<uint32_t*>(&c);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) w[j] = f2bf_rne(v[2 * j]) | (f2bf_rne(v[2 * j + 1]) << 16);
+  c.x = f2bf_rne(v[0]) | (f2bf_rne(v[1]) << 16);
+  c.y = f2bf_rne(v[2]) | (f2bf_rne(v[3]) << 16);
+  c.z = f2bf_rne(v[4]) | (f2bf_rne(v[5]) << 16);
+  c.w = f2bf_rne(v[6]) | (f2bf_rne(v[7]) << 16);
   return c;
 }
 
@@ -186,6 +199,32 @@ __device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const 
   }
 }
 
+// As load_site, but 16-bit formats return the stored values without their
+// scale, which is returned instead (1 for FP32/FP64): a hop is linear, so
+// the scale is applied once, in the final accumulate.
+template <typename S, typename T>
+__device__ __forceinline__ T load_site_unscaled(const Field<S>& f, uint32_t i, T* v) {
+  if constexpr (!StoreTraits<S>::scaled) {
+    load_site(f, i, v);
+    return (T)1;
+  } else {
+    using C = typename Field<S>::chunk;
+    const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+    const uint32_t off = i * (uint32_t)sizeof(C);
+    const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+    const float sc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      uint4 q;
+      q.x = c.x; q.y = c.y; q.z = c.z; q.w = c.w;
+      unpack8<S>(q, v + 8 * k);
+    }
+    return sc;
+  }
+}
+
 // --------------------------------------------------------------------------
 // gauge links: per parity, per direction, 9 complex entries (row-major) as
 // separate arrays of length vh:  U[parity][mu][entry][vh] of complex L2.
@@ -228,6 +267,60 @@ __device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu,
 // --------------------------------------------------------------------------
 
 template <typename T> struct cplx { T re, im; };
+
+// Projection straight from the 24 stored halves of a site (three 16-byte
+// chunks, component index (spin * 3 + colour) * 2 + re/im): each output is
+// psi_up + SIGN * (G psi_dn) in FP32.
+__device__ __forceinline__ float half_at(const uint4* q, int k) {
+  const uint32_t w = word(q[k >> 3], (k >> 1) & 3);
+  return (k & 1) ? half_hi(w) : half_lo(w);
+}
+
+template <int MU, int SIGN>
+__device__ __forceinline__ void project_h(const uint4* q, float* h) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float u0r = half_at(q, (0 * 3 + c) * 2), u0i = half_at(q, (0 * 3 + c) * 2 + 1);
+    const float u1r = half_at(q, (1 * 3 + c) * 2), u1i = half_at(q, (1 * 3 + c) * 2 + 1);
+    const float d2r = half_at(q, (2 * 3 + c) * 2), d2i = half_at(q, (2 * 3 + c) * 2 + 1);
+    const float d3r = half_at(q, (3 * 3 + c) * 2), d3i = half_at(q, (3 * 3 + c) * 2 + 1);
+    constexpr float S = (float)SIGN;
+    float h0r, h0i, h1r, h1i;
+    if constexpr (MU == 0) {
+      h0r = __builtin_fmaf(S, d3i, u0r); h0i = __builtin_fmaf(-S, d3r, u0i);
+      h1r = __builtin_fmaf(S, d2i, u1r); h1i = __builtin_fmaf(-S, d2r, u1i);
+    } else if constexpr (MU == 1) {
+      h0r = __builtin_fmaf(-S, d3r, u0r); h0i = __builtin_fmaf(-S, d3i, u0i);
+      h1r = __builtin_fmaf(S, d2r, u1r); h1i = __builtin_fmaf(S, d2i, u1i);
+    } else if constexpr (MU == 2) {
+      h0r = __builtin_fmaf(S, d2i, u0r); h0i = __builtin_fmaf(-S, d2r, u0i);
+      h1r = __builtin_fmaf(-S, d3i, u1r); h1i = __builtin_fmaf(S, d3r, u1i);
+    } else {
+      h0r = __builtin_fmaf(S, d2r, u0r); h0i = __builtin_fmaf(S, d2i, u0i);
+      h1r = __builtin_fmaf(S, d3r, u1r); h1i = __builtin_fmaf(S, d3i, u1i);
+    }
+    h[(0 * 3 + c) * 2] = h0r; h[(0 * 3 + c) * 2 + 1] = h0i;
+    h[(1 * 3 + c) * 2] = h1r; h[(1 * 3 + c) * 2 + 1] = h1i;
+  }
+}
+
+// the raw 16-bit values of a site and its scale
+template <typename S>
+__device__ __forceinline__ float load_site_raw16(const Field<S>& f, uint32_t i, uint4* q) {
+  using C = typename Field<S>::chunk;
+  const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+  const uint32_t off = i * (uint32_t)sizeof(C);
+  const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+    q[k].x = c.x; q[k].y = c.y; q[k].z = c.z; q[k].w = c.w;
+  }
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
+}
+
+
 
 template <int MU, int SIGN, typename T>
 __device__ __forceinline__ void project(const T* p, T* h) {
@@ -283,6 +376,35 @@ __device__ __forceinline__ void reconstruct_add(const T* g, T* acc) {
 
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += sc [ g ; s G^dag g ]  (reconstruct_add with a scale folded into FMAs)
+template <int MU, int SIGN, typename T>
+__device__ __forceinline__ void reconstruct_fma(const T* g, T sc, T* acc) {
+  const T ss = SIGN * sc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T g0r = g[(0 * 3 + c) * 2], g0i = g[(0 * 3 + c) * 2 + 1];
+    const T g1r = g[(1 * 3 + c) * 2], g1i = g[(1 * 3 + c) * 2 + 1];
+    acc[(0 * 3 + c) * 2] = fmadd(sc, g0r, acc[(0 * 3 + c) * 2]);
+    acc[(0 * 3 + c) * 2 + 1] = fmadd(sc, g0i, acc[(0 * 3 + c) * 2 + 1]);
+    acc[(1 * 3 + c) * 2] = fmadd(sc, g1r, acc[(1 * 3 + c) * 2]);
+    acc[(1 * 3 + c) * 2 + 1] = fmadd(sc, g1i, acc[(1 * 3 + c) * 2 + 1]);
+    T l0r, l0i, l1r, l1i;
+    if constexpr (MU == 0) {
+      l0r = -g1i; l0i = g1r; l1r = -g0i; l1i = g0r;
+    } else if constexpr (MU == 1) {
+      l0r = g1r; l0i = g1i; l1r = -g0r; l1i = -g0i;
+    } else if constexpr (MU == 2) {
+      l0r = -g0i; l0i = g0r; l1r = g1i; l1i = -g1r;
+    } else {
+      l0r = g0r; l0i = g0i; l1r = g1r; l1i = g1i;
+    }
+    acc[(2 * 3 + c) * 2] = fmadd(ss, l0r, acc[(2 * 3 + c) * 2]);
+    acc[(2 * 3 + c) * 2 + 1] = fmadd(ss, l0i, acc[(2 * 3 + c) * 2 + 1]);
+    acc[(3 * 3 + c) * 2] = fmadd(ss, l1r, acc[(3 * 3 + c) * 2]);
+    acc[(3 * 3 + c) * 2 + 1] = fmadd(ss, l1i, acc[(3 * 3 + c) * 2 + 1]);
+  }
+}
 
 // g = U h (DAG = false) or U^dag h (DAG = true), for the two spins of h;
 // every complex product-accumulate is four fused multiply-adds

@@ -27,16 +27,15 @@ template <typename S> inline Field<S> typed(const FieldPtr& f) {
 }
 
 // Fused epilogue after a hop, per 5D site (x, s) and chirality chi:
-//   y(s)   = E0 w(s) [or w(s) if w_identity] + E1 h(s) [or h(s) if E1 null]
-//   out(s) = E2 y(s) [or y(s) if E2 null]
+//   out(s) = E0 w(s) [or w(s) if w_identity] + E1 h(s) [or h(s) if E1 null]
 // with Ls x Ls real matrices per chirality ([2][Ls][Ls], calc precision).
-// If norm_partial is set, each block writes sum |y|^2 of its sites.
+// If dot_partial is set, each block writes Re<dotf, out> over its sites.
 struct Epilogue {
   const void* E0 = nullptr;
   const void* E1 = nullptr;
-  const void* E2 = nullptr;
   bool w_identity = false;
-  double* norm_partial = nullptr;
+  double* dot_partial = nullptr;
+  const FieldPtr* dotf = nullptr;
 };
 
 struct HopGeometry {
@@ -50,7 +49,9 @@ enum ScalarSlot { SLOT_RHO = 0, SLOT_PAP, SLOT_ALPHA, SLOT_BETA, SLOT_RR, SLOT_R
                   SLOT_COUNT = 16 };
 enum FinishMode { FIN_STORE = 0, FIN_ALPHA, FIN_RHO, FIN_BETA_FR, FIN_BETA_PR };
 
+// sites per block of the site kernels (16 when the MFMA epilogue is used)
 int sites_per_block(int Ls, Prec p);
+bool uses_mfma(int Ls, Prec p);
 int64_t full_blocks(int64_t vh, int Ls, Prec p);
 
 // ---------------------------------------------------------------- site kernels

@@ -16,9 +16,12 @@ namespace mspcg {
                                                    hipGetErrorString(e_));            \
   } while (0)
 
+bool uses_mfma(int Ls, Prec p) { return p != Prec::F64 && Ls <= 16; }
+
 int sites_per_block(int Ls, Prec p) {
+  if (uses_mfma(Ls, p)) return 16;
   // blocks of <= 256 threads; FP64 tiles kept small for occupancy; the LDS
-  // of the widest site kernel (two tiles and three matrices) stays <= 60 KB
+  // of the widest site kernel (two tiles and the matrices) stays <= 60 KB
   int ns = 256 / Ls;
   if (p == Prec::F64 && ns > 8) ns = 8;
   const size_t elem = p == Prec::F64 ? 8 : 4;
@@ -34,29 +37,41 @@ int64_t full_blocks(int64_t vh, int Ls, Prec p) {
 
 // ---------------------------------------------------------------- hop launch
 
-template <typename Geo, typename S>
-static void launch_hop(hipStream_t st, const Geo& geo, int64_t nblocks, const FieldPtr& out, const FieldPtr& in,
-                       const FieldPtr* w, int Ls, int ns, bool dagger, const Epilogue& epi) {
+template <typename Geo, typename S, bool MF>
+static void launch_hop_mf(hipStream_t st, const Geo& geo, int64_t nblocks, const FieldPtr& out, const FieldPtr& in,
+                          const FieldPtr* w, int Ls, int ns, bool dagger, const Epilogue& epi) {
   using T = calc_t<S>;
-  const size_t lds = site_lds_bytes<T>(ns, Ls, w != nullptr && !epi.w_identity);
+  const bool tileB = w != nullptr && !epi.w_identity && epi.E0 != nullptr;
+  const size_t lds = site_lds_bytes<T>(ns, Ls, tileB, MF);
   Field<S> wf = w ? typed<S>(*w) : Field<S>{};
+  Field<S> df = epi.dotf ? typed<S>(*epi.dotf) : Field<S>{};
   const T* E0 = (const T*)epi.E0;
   const T* E1 = (const T*)epi.E1;
-  const T* E2 = (const T*)epi.E2;
   dim3 grid((unsigned)nblocks), block(site_block_threads(ns, Ls));
   const int wid = epi.w_identity ? 1 : 0;
   if (dagger) {
-    if (w) hipLaunchKernelGGL((k_hop<Geo, S, true, true>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
-                              Ls, ns, E0, E1, E2, wid, epi.norm_partial);
-    else hipLaunchKernelGGL((k_hop<Geo, S, true, false>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
-                            Ls, ns, E0, E1, E2, wid, epi.norm_partial);
+    if (w) hipLaunchKernelGGL((k_hop<Geo, S, true, true, MF>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
+                              df, Ls, ns, E0, E1, wid, epi.dot_partial);
+    else hipLaunchKernelGGL((k_hop<Geo, S, true, false, MF>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in),
+                            wf, df, Ls, ns, E0, E1, wid, epi.dot_partial);
   } else {
-    if (w) hipLaunchKernelGGL((k_hop<Geo, S, false, true>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
-                              Ls, ns, E0, E1, E2, wid, epi.norm_partial);
-    else hipLaunchKernelGGL((k_hop<Geo, S, false, false>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in), wf,
-                            Ls, ns, E0, E1, E2, wid, epi.norm_partial);
+    if (w) hipLaunchKernelGGL((k_hop<Geo, S, false, true, MF>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in),
+                              wf, df, Ls, ns, E0, E1, wid, epi.dot_partial);
+    else hipLaunchKernelGGL((k_hop<Geo, S, false, false, MF>), grid, block, lds, st, geo, typed<S>(out), typed<S>(in),
+                            wf, df, Ls, ns, E0, E1, wid, epi.dot_partial);
   }
   LAUNCH_CHECK();
+}
+
+template <typename Geo, typename S>
+static void launch_hop(hipStream_t st, const Geo& geo, int64_t nblocks, const FieldPtr& out, const FieldPtr& in,
+                       const FieldPtr* w, int Ls, int ns, bool dagger, const Epilogue& epi) {
+  if constexpr (std::is_same<S, double>::value) {
+    launch_hop_mf<Geo, S, false>(st, geo, nblocks, out, in, w, Ls, ns, dagger, epi);
+  } else {
+    if (uses_mfma(Ls, out.prec)) launch_hop_mf<Geo, S, true>(st, geo, nblocks, out, in, w, Ls, ns, dagger, epi);
+    else launch_hop_mf<Geo, S, false>(st, geo, nblocks, out, in, w, Ls, ns, dagger, epi);
+  }
 }
 
 template <typename S>

@@ -88,6 +88,7 @@ enum MatId {
   MAT_NEG_MPHI_T,   // -M_phi^dag
   MAT_M5,
   MAT_M5INV,
+  MAT_NEG_M5INVT_M5INV,   // -M5^-dag M5^-1
   MAT_COUNT
 };
 
@@ -140,6 +141,17 @@ Mats build_mats(int Ls, double b, double c, double M5, double mf) {
   put(MAT_NEG_MPHI_T, Mp, -1.0, true);
   put(MAT_M5, M5m, 1.0, false);
   put(MAT_M5INV, Minv, 1.0, false);
+  for (int chi = 0; chi < 2; ++chi) {
+    const double* At = M.at(MAT_M5INV_T, chi);
+    const double* B = M.at(MAT_M5INV, chi);
+    double* o = M.at(MAT_NEG_M5INVT_M5INV, chi);
+    for (int s = 0; s < Ls; ++s)
+      for (int t = 0; t < Ls; ++t) {
+        double acc = 0;
+        for (int u = 0; u < Ls; ++u) acc += At[s * Ls + u] * B[u * Ls + t];
+        o[s * Ls + t] = -acc;
+      }
+  }
   return M;
 }
 
@@ -413,24 +425,27 @@ struct mspcg_ctx {
     ev_end(st, e);
   }
 
-  Epilogue epi(Prec p, int e0, int e1, int e2, bool wid = false, double* norm = nullptr) const {
+  Epilogue epi(Prec p, int e0, int e1, bool wid = false, double* dot = nullptr, const FieldPtr* dotf = nullptr) const {
     Epilogue E;
     E.E0 = e0 >= 0 ? mat(p, e0) : nullptr;
     E.E1 = e1 >= 0 ? mat(p, e1) : nullptr;
-    E.E2 = e2 >= 0 ? mat(p, e2) : nullptr;
     E.w_identity = wid;
-    E.norm_partial = norm;
+    E.dot_partial = dot;
+    E.dotf = dotf;
     return E;
   }
 
-  // A = D^dag D on p, given t0 = M_phi p.  norm_partial gets |D p|^2 = <p, A p>.
+  // A = D^dag D on p, given t0 = M_phi p (eq. detail, four hops):
+  //   a = Q D^w t0,  c = M5^-dag p - M5^-dag M5^-1 D^w a  (= M5^-dag D p),
+  //   e = Q^dag D^w^dag c,  out = M5^dag c - M_phi^dag D^w^dag e  (= D^dag D p).
+  // dot_partial gets <p, A p> per block of the last hop.
   void A_from_t0(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr& t0,
-                 const std::string& tag, double* norm_partial) {
+                 const std::string& tag, double* dot_partial) {
     FieldPtr a = field(tag + ".a", p, lat.vh), c = field(tag + ".c", p, lat.vh), e = field(tag + ".e", p, lat.vh);
-    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q, -1), 1);
-    hop(st, p, c, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, MAT_M5INV_T, true, norm_partial), 2);
-    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT, -1), 3);
-    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, -1), 4);
+    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q), 1);
+    hop(st, p, c, a, &in, 0, false, epi(p, MAT_M5INV_T, MAT_NEG_M5INVT_M5INV), 2);
+    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT), 3);
+    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, false, dot_partial, &in), 4);
   }
 
   void A_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag,
@@ -443,20 +458,20 @@ struct mspcg_ctx {
   void D_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag) {
     FieldPtr t0 = field(tag + ".t0", p, lat.vh), a = field(tag + ".a", p, lat.vh);
     apply5_full(st, p, t0, in, mat(p, MAT_MPHI), lat.vh, Ls, nullptr);
-    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q, -1));
-    hop(st, p, out, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, -1, true));
+    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q));
+    hop(st, p, out, a, &in, 0, false, epi(p, -1, MAT_NEG_M5INV, true));
   }
 
   void Ddag_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag) {
     FieldPtr t0 = field(tag + ".t0", p, lat.vh), e = field(tag + ".e", p, lat.vh);
     apply5_full(st, p, t0, in, mat(p, MAT_M5INV_T), lat.vh, Ls, nullptr);
-    hop(st, p, e, t0, nullptr, 1, true, epi(p, -1, MAT_QT, -1));
-    hop(st, p, out, e, &in, 0, true, epi(p, -1, MAT_NEG_MPHI_T, -1, true));
+    hop(st, p, e, t0, nullptr, 1, true, epi(p, -1, MAT_QT));
+    hop(st, p, out, e, &in, 0, true, epi(p, -1, MAT_NEG_MPHI_T, true));
   }
 
   // A_s p_s for every subdomain (inner storage I), given t0 = M_phi p_s on C.
-  // pAp partials [d][bps of h2] when norm != null.
-  void Asub(hipStream_t st, Prec I, const FieldPtr& q, const FieldPtr& ps, const FieldPtr& t0, double* norm) {
+  // <p_s, A_s p_s> partials [d][bps of C] when dot != null.
+  void Asub(hipStream_t st, Prec I, const FieldPtr& q, const FieldPtr& ps, const FieldPtr& t0, double* dot) {
     FieldPtr a = field("in.a", I, (int64_t)nsub * nN1), c = field("in.c", I, (int64_t)nsub * nN2),
              e = field("in.e", I, (int64_t)nsub * nN1);
     auto run = [&](int which, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int par, bool dag,
@@ -465,10 +480,10 @@ struct mspcg_ctx {
       hop_sub(st, I, out, in, w, gauge(I), lat, par, tables(which, I), nsub, Ls, dag, E);
       ev_end(st, ev);
     };
-    run(1, a, t0, nullptr, 1, false, epi(I, -1, MAT_Q, -1));
-    run(2, c, a, &ps, 0, false, epi(I, -1, MAT_NEG_M5INV, MAT_M5INV_T, true, norm));
-    run(3, e, c, nullptr, 1, true, epi(I, -1, MAT_QT, -1));
-    run(4, q, e, &c, 0, true, epi(I, MAT_M5_T, MAT_NEG_MPHI_T, -1));
+    run(1, a, t0, nullptr, 1, false, epi(I, -1, MAT_Q));
+    run(2, c, a, &ps, 0, false, epi(I, MAT_M5INV_T, MAT_NEG_M5INVT_M5INV));
+    run(3, e, c, nullptr, 1, true, epi(I, -1, MAT_QT));
+    run(4, q, e, &c, 0, true, epi(I, MAT_M5_T, MAT_NEG_MPHI_T, false, dot, &ps));
   }
 
   // z = (+)_s CG_k(A_s, R_s r).  Outer precision O for r, z, r_old.
@@ -484,15 +499,15 @@ struct mspcg_ctx {
     sc.alpha = buf("in.alpha", nsub * sizeof(double)).as<double>();
     sc.beta = buf("in.beta", nsub * sizeof(double)).as<double>();
     sc.active = buf("in.active", nsub * sizeof(int)).as<int>();
-    const SubTables tc = tables(0, I), t2 = tables(2, I);
+    const SubTables tc = tables(0, I);
     double* prr = partial("in.rr", (int64_t)nsub * tc.bps);
-    double* ppap = partial("in.pap", (int64_t)nsub * t2.bps);
+    double* ppap = partial("in.pap", (int64_t)nsub * tc.bps);
     sub_restrict(st, O, I, r, rs, ps, t0, mat(I, MAT_MPHI), lat, tc, nsub, Ls, prr);
     sub_finish(st, prr, tc.bps, nsub, sc, SUB_INIT);
     for (int it = 0; it < k; ++it) {
       if (it > 0) sub_xpay5(st, I, ps, rs, t0, sc, mat(I, MAT_MPHI), tc, nsub, Ls);
       Asub(st, I, qs, ps, t0, ppap);
-      sub_finish(st, ppap, t2.bps, nsub, sc, SUB_ALPHA);
+      sub_finish(st, ppap, tc.bps, nsub, sc, SUB_ALPHA);
       sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, prr);
       sub_finish(st, prr, tc.bps, nsub, sc, SUB_BETA);
     }

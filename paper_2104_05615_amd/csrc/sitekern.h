@@ -8,11 +8,23 @@
 // the fifth dimension within one chirality, read it directly.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace mspcg {
 
 template <typename S> using calc_t = typename StoreTraits<S>::calc;
+
+// Register fence between the directions of a hop: the 24 accumulators are
+// final here and no later memory access moves above this point.  Without it
+// the compiler overlaps all eight neighbour terms and needs every register.
+template <typename T>
+__device__ __forceinline__ void pin(T* acc) {
+#pragma unroll
+  for (int k = 0; k < 24; ++k) asm volatile("" : "+v"(acc[k]));
+  asm volatile("" ::: "memory");
+}
 
 // padded row stride (elements) of one site's [Ls][24] tile in LDS
 __host__ __device__ inline int tile_stride(int Ls) { return Ls * 24 + 4; }
@@ -28,6 +40,29 @@ struct SiteRef {
   int64_t out5;   // 5D index of the output
   int64_t w5;     // 5D index of the centre field, or -1 when it vanishes there
 };
+
+// load a neighbour and project it: h = (1 + SIGN gamma_mu) psi (upper half);
+// returns the factor the reconstruction multiplies by (the 16-bit scale)
+template <int MU, int SIGN, typename S, typename T>
+__device__ __forceinline__ T load_project(const Field<S>& in, uint32_t i, T* h) {
+  if constexpr (std::is_same<S, __half>::value) {
+    uint4 q[3];
+    const float sc = load_site_raw16(in, i, q);
+    project_h<MU, SIGN>(q, h);
+    return sc;
+  } else {
+    T psi[24];
+    const T sc = load_site_unscaled(in, i, psi);
+    project<MU, SIGN>(psi, h);
+    return sc;
+  }
+}
+
+template <int MU, int SIGN, typename S, typename T>
+__device__ __forceinline__ void accumulate(const T* gh, T sc, T* acc) {
+  if constexpr (StoreTraits<S>::scaled) reconstruct_fma<MU, SIGN>(gh, sc, acc);
+  else reconstruct_add<MU, SIGN>(gh, acc);
+}
 
 // ---------------------------------------------------------------- full lattice
 
@@ -57,17 +92,15 @@ template <typename T> struct FullGeo {
     const uint32_t lf = (c[MU] + 1 == L) ? lx - (uint32_t)(L - 1) * st : lx + st;
     const uint32_t lb = (c[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
     const uint32_t jf = lf >> 1, jb = lb >> 1;
-    T psi[24], h[12], gh[12], u[18];
-    load_site(in, jf * (uint32_t)Ls + (uint32_t)s, psi);
-    project<MU, SF>(psi, h);
+    T h[12], gh[12], u[18];
+    T sc = load_project<MU, SF>(in, jf * (uint32_t)Ls + (uint32_t)s, h);
     load_link(g, par, MU, site, u);
     su3_mul_half<false>(u, h, gh);
-    reconstruct_add<MU, SF>(gh, acc);
-    load_site(in, jb * (uint32_t)Ls + (uint32_t)s, psi);
-    project<MU, SB>(psi, h);
+    accumulate<MU, SF, S>(gh, sc, acc);
+    sc = load_project<MU, SB>(in, jb * (uint32_t)Ls + (uint32_t)s, h);
     load_link(g, 1 - par, MU, jb, u);
     su3_mul_half<true>(u, h, gh);
-    reconstruct_add<MU, SB>(gh, acc);
+    accumulate<MU, SB, S>(gh, sc, acc);
   }
 
   template <bool DAG, typename S>
@@ -79,8 +112,11 @@ template <typename T> struct FullGeo {
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
     dir<0, DAG>(in, c, lx, site, s, Ls, acc);
+    pin(acc);
     dir<1, DAG>(in, c, lx, site, s, Ls, acc);
+    pin(acc);
     dir<2, DAG>(in, c, lx, site, s, Ls, acc);
+    pin(acc);
     dir<3, DAG>(in, c, lx, site, s, Ls, acc);
   }
 };
@@ -114,24 +150,22 @@ template <typename T> struct SubGeo {
                                       const int* nb, int s, int Ls, T* acc) const {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
-    T psi[24], h[12], gh[12], u[18];
+    T h[12], gh[12], u[18];
     const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
     if (jf >= 0) {
-      load_site(in, (base_in + (uint32_t)jf) * (uint32_t)Ls + (uint32_t)s, psi);
-      project<MU, SF>(psi, h);
+      const T sc = load_project<MU, SF>(in, (base_in + (uint32_t)jf) * (uint32_t)Ls + (uint32_t)s, h);
       load_link(g, par, MU, lx >> 1, u);
       su3_mul_half<false>(u, h, gh);
-      reconstruct_add<MU, SF>(gh, acc);
+      accumulate<MU, SF, S>(gh, sc, acc);
     }
     if (jb >= 0) {
       const int L = lat.ext(MU);
       const uint32_t st = lat.stride(MU);
       const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
-      load_site(in, (base_in + (uint32_t)jb) * (uint32_t)Ls + (uint32_t)s, psi);
-      project<MU, SB>(psi, h);
+      const T sc = load_project<MU, SB>(in, (base_in + (uint32_t)jb) * (uint32_t)Ls + (uint32_t)s, h);
       load_link(g, 1 - par, MU, lb >> 1, u);
       su3_mul_half<true>(u, h, gh);
-      reconstruct_add<MU, SB>(gh, acc);
+      accumulate<MU, SB, S>(gh, sc, acc);
     }
   }
 
@@ -156,8 +190,11 @@ template <typename T> struct SubGeo {
     const int nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
     const uint32_t base_in = (uint32_t)r.d * (uint32_t)tb.n_in;
     dir<0, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
+    pin(acc);
     dir<1, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
+    pin(acc);
     dir<2, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
+    pin(acc);
     dir<3, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
   }
 };
@@ -206,29 +243,103 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return tot;
 }
 
+// ---------------------------------------------------------------- MFMA epilogue
+//
+// With 16 sites per block (ns = 16) and Ls <= 16 the fifth-dimension matrix
+// products of a block are, per chirality chi and per component c of that
+// chirality, a 16 x 16 matrix product
+//     Y[s][site] = sum_t E_chi[s][t] H[t][site]      (s, t < Ls; padded to 16)
+// i.e. 24 tiles of one v_mfma_f32_16x16x16_f16 (16-bit storage: operands in
+// FP16, every column (site) scaled into [-1, 1] by its largest entry) or of
+// four v_mfma_f32_16x16x4_f32 (FP32).  Lane l of a wavefront holds column
+// l % 16 and the fifth-dimension rows 4 (l / 16) .. 4 (l / 16) + 3.
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <typename S> struct UsesMfma {
+  static constexpr bool value = !std::is_same<S, double>::value;
+  static constexpr bool half_ops = StoreTraits<S>::scaled;   // FP16 operands with column scales
+};
+
+// A operands (the matrix) for one chirality: f16 path
+__device__ __forceinline__ half4_t mfma_a16(const float* E, int chi, int Ls, int lane) {
+  const int i = lane & 15, g = lane >> 4;
+  half4_t a;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int t = 4 * g + v;
+    a[v] = (i < Ls && t < Ls) ? (_Float16)E[(chi * Ls + i) * Ls + t] : (_Float16)0.f;
+  }
+  return a;
+}
+
+// one tile: acc += E_chi H[:, site = lane%16, component q]
+__device__ __forceinline__ float4_t mfma_tile16(half4_t a, const float* tile, int stride, int Ls, int q, float ics,
+                                                int lane, float4_t acc) {
+  const int col = lane & 15, g = lane >> 4;
+  half4_t b;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int t = 4 * g + v;
+    b[v] = t < Ls ? (_Float16)(tile[col * stride + t * 24 + q] * ics) : (_Float16)0.f;
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ float4_t mfma_tile32(const float* E, int chi, const float* tile, int stride, int Ls, int q,
+                                                int lane, float4_t acc) {
+  const int col = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int t = 4 * kk + g;
+    const float a = (col < Ls && t < Ls) ? E[(chi * Ls + col) * Ls + t] : 0.f;
+    const float b = t < Ls ? tile[col * stride + t * 24 + q] : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // LDS layout of the site kernels:
 //   red   [16] doubles            (block reduction scratch)
-//   mats  [3][2][Ls][Ls] of T     (E0, E1, E2)
-//   tileA [ns][tile_stride] of T  (hop result / second-stage input)
-//   tileB [ns][tile_stride] of T  (centre field; only when E0 is dense)
+//   mats  [2][2][Ls][Ls] of T     (E0, E1; VALU path only)
+//   tileA [ns][tile_stride] of T  (hop result)
+//   tileB [ns][tile_stride] of T  (centre field, when E0 is dense)
+//   tileO [ns][tile_stride] of T  (MFMA path with fewer than 3 wavefronts:
+//                                  epilogue result; otherwise tileA is reused)
+//   smax  [ns][Ls] floats         (MFMA path with FP16 operands: column maxima)
 template <typename T>
-inline size_t site_lds_bytes(int ns, int Ls, bool tileB) {
-  return 16 * sizeof(double) + sizeof(T) * (size_t)(6 * Ls * Ls + (tileB ? 2 : 1) * ns * tile_stride(Ls));
+inline size_t site_lds_bytes(int ns, int Ls, bool tileB, bool mfma) {
+  size_t n = 16 * sizeof(double);
+  if (!mfma) n += sizeof(T) * (size_t)(4 * Ls * Ls);
+  n += sizeof(T) * (size_t)((tileB ? 2 : 1) * ns * tile_stride(Ls));
+  if (mfma) {
+    const int nwave = site_block_threads(ns, Ls) / 64;
+    if (nwave < 3) n += sizeof(T) * (size_t)(ns * tile_stride(Ls));
+    n += sizeof(float) * (size_t)(ns * Ls);
+  }
+  return n;
 }
 
 // One hop with the fused epilogue
-//   y = E0 w (or w if w_identity) + E1 h (or h), out = E2 y (or y),
-// and optionally one |y|^2 partial per block.
-template <typename Geo, typename S, bool DAG, bool HASW>
-__global__ void __launch_bounds__(256)
-k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, int Ls, int ns, const calc_t<S>* E0, const calc_t<S>* E1,
-      const calc_t<S>* E2, int w_identity, double* norm_partial) {
+//   y = E0 w (or w if w_identity, or nothing) + E1 h (or h if E1 is null),
+// and optionally one partial of Re<dotf, y> per block (the output's dot with
+// a field read at the output site).  MF selects the MFMA epilogue (ns = 16).
+//
+// Occupancy floor: the hop is latency bound on its neighbour loads.
+template <typename Geo, typename S, bool DAG, bool HASW, bool MF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(calc_t<S>) == 8 ? 2 : 4)))
+k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, Field<S> dotf, int Ls, int ns, const calc_t<S>* E0,
+      const calc_t<S>* E1, int w_identity, double* dot_partial) {
   using T = calc_t<S>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* red = reinterpret_cast<double*>(lds_raw);
   T* mats = reinterpret_cast<T*>(red + 16);
-  T* tileA = mats + 6 * Ls * Ls;
+  T* tileA = MF ? mats : mats + 4 * Ls * Ls;
+  const bool e0_dense = HASW && !w_identity && E0 != nullptr;
   T* tileB = tileA + ns * tile_stride(Ls);
+  T* tileO = tileB + (e0_dense ? ns * tile_stride(Ls) : 0);
+  float* smax = reinterpret_cast<float*>(tileO + ((blockDim.x >> 6) < 3 ? ns * tile_stride(Ls) : 0));
 
   const int tid = threadIdx.x;
   const bool inb = tid < ns * Ls;
@@ -237,11 +348,12 @@ k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, int Ls, int ns, const calc
   const SiteRef r = geo.locate(blk, sl, ns, Ls, s);
   const bool valid = inb && r.valid;
 
-  const int nm = 2 * Ls * Ls;
-  for (int k = tid; k < nm; k += blockDim.x) {
-    if (E0) mats[k] = E0[k];
-    if (E1) mats[nm + k] = E1[k];
-    if (E2) mats[2 * nm + k] = E2[k];
+  if constexpr (!MF) {
+    const int nm = 2 * Ls * Ls;
+    for (int k = tid; k < nm; k += blockDim.x) {
+      if (E0) mats[k] = E0[k];
+      if (E1) mats[nm + k] = E1[k];
+    }
   }
 
   T h[24], y[24];
@@ -260,36 +372,119 @@ k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, int Ls, int ns, const calc
 #pragma unroll
       for (int k = 0; k < 24; ++k) wv[k] = 0;
     }
-    if (!w_identity && inb) tile_put(myB, s, wv);
+    if (e0_dense && inb) tile_put(myB, s, wv);
   }
-  __syncthreads();
-  if (inb && E1) mat5_lds(myA, mats + nm, s, Ls, y, false);
-  else {
+
+  if constexpr (MF) {
+    constexpr bool HO = UsesMfma<S>::half_ops;
+    if (HO && inb) {
+      float m = 0.f;
 #pragma unroll
-    for (int k = 0; k < 24; ++k) y[k] = h[k];
-  }
-  if (HASW) {
-    if (w_identity) {
+      for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)h[k]));
+      if (e0_dense) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)wv[k]));
+      }
+      smax[sl * Ls + s] = m;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6, nwave = (int)(blockDim.x >> 6);
+    const int col = lane & 15, g = lane >> 4;
+    float cs = 1.f, ics = 1.f;
+    if (HO) {
+      cs = 0.f;
+      for (int t = 0; t < Ls; ++t) cs = fmaxf(cs, smax[col * Ls + t]);
+      ics = cs > 0.f ? 1.f / cs : 0.f;
+    }
+    if (E1 || e0_dense) {
+      half4_t a1[2], a0[2];
+      if (HO) {
+#pragma unroll
+        for (int chi = 0; chi < 2; ++chi) {
+          if (E1) a1[chi] = mfma_a16((const float*)E1, chi, Ls, lane);
+          if (e0_dense) a0[chi] = mfma_a16((const float*)E0, chi, Ls, lane);
+        }
+      }
+      auto tile = [&](int q) {
+        const int chi = q / 12;
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        if (HO) {
+          if (E1) acc = mfma_tile16(a1[chi], (const float*)tileA, tile_stride(Ls), Ls, q, ics, lane, acc);
+          if (e0_dense) acc = mfma_tile16(a0[chi], (const float*)tileB, tile_stride(Ls), Ls, q, ics, lane, acc);
+        } else {
+          if (E1) acc = mfma_tile32((const float*)E1, chi, (const float*)tileA, tile_stride(Ls), Ls, q, lane, acc);
+          if (e0_dense) acc = mfma_tile32((const float*)E0, chi, (const float*)tileB, tile_stride(Ls), Ls, q, lane, acc);
+        }
+        return acc;
+      };
+      auto put = [&](T* dst, int q, const float4_t& acc) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int t = 4 * g + v;
+          if (t < Ls) dst[col * tile_stride(Ls) + t * 24 + q] = (T)(acc[v] * cs);
+        }
+      };
+      T* dst;
+      if (nwave >= 3) {
+        // at most 8 tiles per wavefront: keep them in registers, then
+        // overwrite the input tile once every wavefront has read it
+        float4_t accs[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int q = wave + j * nwave;
+          if (q < 24) accs[j] = tile(q);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int q = wave + j * nwave;
+          if (q < 24) put(tileA, q, accs[j]);
+        }
+        dst = tileA;
+      } else {
+        for (int q = wave; q < 24; q += nwave) put(tileO, q, tile(q));
+        dst = tileO;
+      }
+      __syncthreads();
+      if (inb) {
+        const T* o = dst + sl * tile_stride(Ls) + s * 24;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) y[k] = o[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 24; ++k) y[k] = h[k];
+    }
+    if (HASW && w_identity) {
 #pragma unroll
       for (int k = 0; k < 24; ++k) y[k] += wv[k];
-    } else if (inb) {
-      mat5_lds(myB, mats, s, Ls, y, true);
+    }
+  } else {
+    __syncthreads();
+    if (inb && E1) mat5_lds(myA, mats + 2 * Ls * Ls, s, Ls, y, false);
+    else {
+#pragma unroll
+      for (int k = 0; k < 24; ++k) y[k] = h[k];
+    }
+    if (HASW) {
+      if (w_identity) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) y[k] += wv[k];
+      } else if (inb && E0) {
+        mat5_lds(myB, mats, s, Ls, y, true);
+      }
     }
   }
-  if (norm_partial) {
+  if (dot_partial) {
     T loc = 0;
     if (valid) {
+      T pv[24];
+      load_site(dotf, r.out5, pv);
 #pragma unroll
-      for (int k = 0; k < 24; ++k) loc += y[k] * y[k];
+      for (int k = 0; k < 24; ++k) loc += pv[k] * y[k];
     }
     const double tot = block_sum((double)loc, red);
-    if (tid == 0) norm_partial[blk] = tot;
-  }
-  if (E2) {
-    __syncthreads();
-    if (inb) tile_put(myA, s, y);
-    __syncthreads();
-    if (inb) mat5_lds(myA, mats + 2 * nm, s, Ls, y, false);
+    if (tid == 0) dot_partial[blk] = tot;
   }
   if (valid) store_site(out, r.out5, y);
 }
