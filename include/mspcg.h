@@ -94,6 +94,7 @@ typedef struct {
   double iter_rel_resid;  /* iterated residual at exit                                             */
   double ms_total;        /* wall clock of the solve on the device stream                          */
   double ms_precond;      /* part spent in the preconditioner (only when profiling is on)          */
+  int32_t status;         /* mspcg_status of this right-hand side                                  */
 } mspcg_stats;
 
 /* Create a handle for an X*Y*Z*T lattice on HIP device `device`.  No HIP call
@@ -139,6 +140,45 @@ mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0
 mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const double* x0, void* hip_stream,
                                 mspcg_stats* st);
 
+/* Solve A x_r = b_r for nrhs right-hand sides on the loaded gauge field, each
+ * by the same PCG as mspcg_solve_device (Alg. 1 with the reliable updates and
+ * Polak-Ribiere beta of Sec. 3.2, preconditioner of Sec. 2.4-2.5).  Every
+ * kernel of an iteration runs once for all right-hand sides (a hop launch
+ * covers every site block of every RHS); the iteration's convergence,
+ * reliable-update and breakdown decisions are taken on the device per RHS,
+ * a RHS that has stopped drops out of every launch, and two iterations are
+ * captured in a HIP graph and replayed without a host round trip (eagerly
+ * when profiling is on).  Each RHS gets the result and iteration count the
+ * single-RHS solve gives it: same kernels, partitions and reduction orders.
+ *   b, x:  device FP64, nrhs fields of the layout above one after another
+ *          (RHS r at offset r * Ls * V/2 * 24 doubles);  x0: nullable, same.
+ *   st:    nullable, else an array of nrhs stats (status per RHS).
+ * Runs on hip_stream (NULL = the handle's stream); returns when done.
+ * Returns BREAKDOWN if any RHS broke down, else NOT_CONVERGED if any did not
+ * converge, else OK; INVALID_ARG for nrhs outside [1, 1024] or NULL buffers;
+ * NO_GAUGE, NO_PARAMS, BAD_TILING as mspcg_solve. */
+mspcg_status mspcg_solve_batch_device(mspcg_t h, int32_t nrhs, const double* b, double* x, const double* x0,
+                                      void* hip_stream, mspcg_stats* st);
+
+/* Choose the workgroup schedule of the hop kernels for nrhs right-hand sides
+ * by timing the candidates on this handle's lattice, Ls and precisions.  A
+ * hop launch runs one workgroup per (site block, RHS); the candidates are
+ * the RHS order (RHS outermost, or the RHS of one site block adjacent so that
+ * they read its links from one L2) and the XCD mapping (contiguous site-block
+ * ranges per XCD, or the hardware's round robin).  Kinds: 0 = full-lattice
+ * hops in the outer precision, 1 = FP64 hops, 2 = subdomain hops (needs a
+ * tiling).  No schedule changes a result: partial sums are indexed by
+ * (RHS, site block), not by workgroup.  The choice is kept in the handle
+ * until set_mobius / set_subdomains.
+ * Errors: INVALID_ARG (nrhs outside [1, 1024]), NO_GAUGE, NO_PARAMS. */
+mspcg_status mspcg_autotune(mspcg_t h, int32_t nrhs);
+
+/* The schedule in use for (kind, nrhs): RHS order (0 = RHS outermost, 1 = RHS
+ * of a site block adjacent), XCD mapping (1 = contiguous ranges per XCD) and
+ * the tuned time of the kind's four hops in microseconds (0 when untuned).
+ * Errors: INVALID_ARG for NULL or an unknown kind. */
+mspcg_status mspcg_get_schedule(mspcg_t h, int32_t kind, int32_t nrhs, int32_t* order, int32_t* xcd, double* us);
+
 /* Apply one operator (mspcg_op) in precision `prec` to a host FP64 field and
  * return the result as host FP64: the input is converted to the storage of
  * `prec`, the operator runs with that storage, the output is converted back.
@@ -161,6 +201,83 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
  * h1..h4: N1<-C, N2<-N1, N1<-N2, C<-N1).  Counters are reset by set_profiling. */
 mspcg_status mspcg_set_profiling(mspcg_t h, int32_t on);
 mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, double* ms);
+
+/* Use the device gauge field of `src` in `h` (same lattice extents and
+ * device) instead of a copy of its own: the field stays alive while any
+ * handle uses it.  For many solver contexts on one resident field.
+ * Errors: INVALID_ARG (NULL, extents or device differ), NO_GAUGE (src has
+ * none). */
+mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src);
+
+/* Device memory of a handle: `estimate` = bytes a batched solve of nrhs
+ * right-hand sides allocates with the current parameters (workspaces,
+ * matrices, tables; not the gauge field), `allocated` = bytes the handle
+ * holds now.  Errors: INVALID_ARG, NO_PARAMS. */
+mspcg_status mspcg_footprint(mspcg_t h, int32_t nrhs, int64_t* estimate, int64_t* allocated);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop on one device over resident gauge fields.
+ *
+ * Requests (a batched solve: field, Mobius parameters, tiling, solver
+ * parameters, nrhs device sources and solutions) are admitted in arrival
+ * order while fewer than max_inflight run and their device footprint fits
+ * the HBM budget; each admitted request runs on its own worker thread and
+ * HIP stream, so requests overlap on the device, and a request that arrives
+ * while others run is admitted as soon as a slot and the memory free up
+ * (continuous batching).  Solver contexts stay resident between requests,
+ * one per (field, Ls, b, c, M5, mf, tiling) in use, and are reused by later
+ * requests of the same shape; idle contexts are evicted least recently used
+ * when the budget needs their memory.  A request's result does not depend
+ * on what runs beside it.
+ * ------------------------------------------------------------------------- */
+typedef struct mspcg_server* mspcg_server_t;
+
+typedef struct {
+  int32_t field;                /* from mspcg_server_add_field                       */
+  int32_t Ls;
+  double b, c, M5, mf;          /* Mobius parameters (as mspcg_set_mobius)            */
+  int32_t sub[4];               /* subdomain extents (as mspcg_set_subdomains)        */
+  mspcg_solver_params solver;
+  int32_t nrhs;                 /* 1..1024                                            */
+  const double* src;            /* device FP64, nrhs fields one after another; ready  */
+  double* x;                    /*   before submit, untouched by the caller until wait */
+} mspcg_request;
+
+typedef struct {
+  int64_t budget;               /* HBM budget in bytes                                */
+  int64_t bytes_in_use;         /* gauge fields + resident contexts + reservations   */
+  int64_t bytes_peak;
+  int32_t inflight, waiting, peak_inflight, contexts;
+  int64_t completed, evictions;
+} mspcg_server_stats;
+
+/* Start a server on `device` with an HBM budget (bytes) and at most
+ * max_inflight concurrent requests (1..64).  Errors: INVALID_ARG. */
+mspcg_status mspcg_server_create(mspcg_server_t* out, int32_t device, int64_t hbm_budget, int32_t max_inflight);
+
+/* Finish the requests in flight and waiting, then free everything. */
+mspcg_status mspcg_server_destroy(mspcg_server_t s);
+
+/* Load a gauge field (host FP64, layout above) onto the device; it stays
+ * resident until the server is destroyed.  *field gets its id.
+ * Errors: INVALID_ARG, OOM (the field does not fit the budget), HIP. */
+mspcg_status mspcg_server_add_field(mspcg_server_t s, const int32_t dims[4], const double* U, int32_t* field);
+
+/* Queue a request; *ticket identifies it.  Returns at once.
+ * Errors: INVALID_ARG (NULL, unknown field, nrhs outside [1, 1024]). */
+mspcg_status mspcg_server_submit(mspcg_server_t s, const mspcg_request* r, int64_t* ticket);
+
+/* *done = 1 when the request has finished.  Errors: INVALID_ARG (ticket). */
+mspcg_status mspcg_server_poll(mspcg_server_t s, int64_t ticket, int32_t* done);
+
+/* Wait for a request, fill st[nrhs] (nullable) and *latency_ms (nullable:
+ * submit to completion, host wall clock) and release the ticket.  Returns
+ * the request's status (as mspcg_solve_batch_device; OOM when it cannot fit
+ * the budget even alone; BAD_TILING or INVALID_ARG for bad parameters). */
+mspcg_status mspcg_server_wait(mspcg_server_t s, int64_t ticket, mspcg_stats* st, double* latency_ms);
+
+/* Counters of the server. */
+mspcg_status mspcg_server_info(mspcg_server_t s, mspcg_server_stats* info);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char* mspcg_last_error(void);

@@ -65,7 +65,20 @@ class mspcg_stats(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("inner_iters_total", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("true_rel_resid", ctypes.c_double),
                 ("iter_rel_resid", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("ms_precond", ctypes.c_double)]
+                ("ms_precond", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+class mspcg_request(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_int32), ("Ls", ctypes.c_int32), ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("M5", ctypes.c_double), ("mf", ctypes.c_double), ("sub", ctypes.c_int32 * 4),
+                ("solver", mspcg_solver_params), ("nrhs", ctypes.c_int32), ("src", ctypes.c_void_p),
+                ("x", ctypes.c_void_p)]
+
+
+class mspcg_server_stats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_int64), ("bytes_in_use", ctypes.c_int64), ("bytes_peak", ctypes.c_int64),
+                ("inflight", ctypes.c_int32), ("waiting", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
+                ("contexts", ctypes.c_int32), ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64)]
 
 
 _h = ctypes.c_void_p
@@ -81,6 +94,18 @@ _SIGS = {
     "mspcg_set_solver": [_h, ctypes.POINTER(mspcg_solver_params)],
     "mspcg_solve": [_h, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
     "mspcg_solve_device": [_h, _p, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
+    "mspcg_solve_batch_device": [_h, _i32, _p, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
+    "mspcg_autotune": [_h, _i32],
+    "mspcg_share_gauge": [_h, _h],
+    "mspcg_footprint": [_h, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "mspcg_server_create": [ctypes.POINTER(_h), _i32, ctypes.c_int64, _i32],
+    "mspcg_server_destroy": [_h],
+    "mspcg_server_add_field": [_h, ctypes.POINTER(_i32), _p, ctypes.POINTER(_i32)],
+    "mspcg_server_submit": [_h, ctypes.POINTER(mspcg_request), ctypes.POINTER(ctypes.c_int64)],
+    "mspcg_server_poll": [_h, ctypes.c_int64, ctypes.POINTER(_i32)],
+    "mspcg_server_wait": [_h, ctypes.c_int64, ctypes.POINTER(mspcg_stats), ctypes.POINTER(_d)],
+    "mspcg_server_info": [_h, ctypes.POINTER(mspcg_server_stats)],
+    "mspcg_get_schedule": [_h, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_d)],
     "mspcg_apply": [_h, _i32, ctypes.c_int, _p, _p],
     "mspcg_apply_device": [_h, _i32, ctypes.c_int, _p, _p, _p],
     "mspcg_set_profiling": [_h, _i32],
@@ -131,9 +156,18 @@ class Stats:
     ms_precond: float
 
 
+def _solver_params(tol=1e-10, maxiter=10000, inner_iters=6, inner_prec="fp16", outer_prec="fp32",
+                   reliable_delta=0.1, beta_rule="PR", use_precond=True):
+    return mspcg_solver_params(float(tol), int(maxiter), int(inner_iters), PREC[inner_prec], PREC[outer_prec],
+                               float(reliable_delta), 0 if beta_rule == "PR" else 1, 1 if use_precond else 0)
+
+
 def _stats(st, s):
     return Stats(st, s.outer_iters, s.inner_iters_total, s.reliable_updates, s.true_rel_resid,
                  s.iter_rel_resid, s.ms_total, s.ms_precond)
+
+
+KIND_OUTER, KIND_FP64, KIND_INNER = 0, 1, 2
 
 
 class MSPCG:
@@ -173,9 +207,17 @@ class MSPCG:
 
     def set_solver(self, tol=1e-10, maxiter=10000, inner_iters=6, inner_prec="fp16", outer_prec="fp32",
                    reliable_delta=0.1, beta_rule="PR", use_precond=True):
-        p = mspcg_solver_params(float(tol), int(maxiter), int(inner_iters), PREC[inner_prec], PREC[outer_prec],
-                                float(reliable_delta), 0 if beta_rule == "PR" else 1, 1 if use_precond else 0)
+        p = _solver_params(tol, maxiter, inner_iters, inner_prec, outer_prec, reliable_delta, beta_rule, use_precond)
         _check(mspcg_set_solver(self._h, ctypes.byref(p)))
+
+    def share_gauge(self, other):
+        _check(mspcg_share_gauge(self._h, other._h))
+
+    def footprint(self, nrhs=1):
+        """(bytes a batched solve of nrhs allocates, bytes held now)."""
+        e, a = ctypes.c_int64(), ctypes.c_int64()
+        _check(mspcg_footprint(self._h, int(nrhs), ctypes.byref(e), ctypes.byref(a)))
+        return e.value, a.value
 
     def _n(self):
         return self.Ls * self.vh * 24
@@ -196,6 +238,23 @@ class MSPCG:
                     allow_not_converged=True)
         return _stats(st, s)
 
+    def solve_batch_device(self, nrhs, b_ptr, x_ptr, x0_ptr=None, stream=None):
+        """nrhs device FP64 fields one after another; returns (status, [Stats per RHS])."""
+        arr = (mspcg_stats * int(nrhs))()
+        st = mspcg_solve_batch_device(self._h, int(nrhs), b_ptr, x_ptr, x0_ptr, stream, arr)
+        if st not in (MSPCG_OK, MSPCG_NOT_CONVERGED, MSPCG_ERR_BREAKDOWN):
+            _check(st)
+        return st, [_stats(a.status, a) for a in arr]
+
+    def autotune(self, nrhs=1):
+        _check(mspcg_autotune(self._h, int(nrhs)))
+
+    def schedule(self, kind, nrhs=1):
+        """(RHS order, XCD mapping, tuned microseconds) of a hop kind (KIND_*)."""
+        o, x, us = _i32(), _i32(), _d()
+        _check(mspcg_get_schedule(self._h, int(kind), int(nrhs), ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)))
+        return o.value, x.value, us.value
+
     def apply(self, op, prec, psi):
         a = _host_f64(psi, self._n())
         out = np.empty(self._n(), dtype=np.float64)
@@ -215,3 +274,62 @@ class MSPCG:
         ms = ctypes.c_double()
         _check(mspcg_get_kernel_time(self._h, int(kind), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+
+class Server:
+    """A request loop (``mspcg_server_t``) on one device."""
+
+    def __init__(self, device=0, hbm_budget=64 << 30, max_inflight=4):
+        h = _h()
+        _check(mspcg_server_create(ctypes.byref(h), int(device), int(hbm_budget), int(max_inflight)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            mspcg_server_destroy(self._h)
+            self._h = _h()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_field(self, dims, U):
+        X, Y, Z, T = (int(d) for d in dims)
+        u = _host_f64(U, X * Y * Z * T * 4 * 9 * 2)
+        f = _i32()
+        _check(mspcg_server_add_field(self._h, (_i32 * 4)(X, Y, Z, T), u.ctypes.data, ctypes.byref(f)))
+        return f.value
+
+    def submit(self, field, Ls, b, c, M5, mf, sub, nrhs, src_ptr, x_ptr, **solver):
+        """src_ptr / x_ptr: device FP64 buffers of nrhs fields, src ready before the call."""
+        r = mspcg_request(int(field), int(Ls), float(b), float(c), float(M5), float(mf),
+                          (_i32 * 4)(*[int(v) for v in (sub or (0, 0, 0, 0))]), _solver_params(**solver),
+                          int(nrhs), src_ptr, x_ptr)
+        t = ctypes.c_int64()
+        _check(mspcg_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._nrhs = getattr(self, "_nrhs", {})
+        self._nrhs[t.value] = int(nrhs)
+        return t.value
+
+    def poll(self, ticket):
+        d = _i32()
+        _check(mspcg_server_poll(self._h, int(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket):
+        """(status, [Stats per RHS], latency in ms); errors other than the
+        solve outcomes (OK, NOT_CONVERGED, BREAKDOWN, OOM) raise."""
+        n = self._nrhs.pop(int(ticket), 1)
+        arr = (mspcg_stats * n)()
+        lat = _d()
+        st = mspcg_server_wait(self._h, int(ticket), arr, ctypes.byref(lat))
+        if st not in (MSPCG_OK, MSPCG_NOT_CONVERGED, MSPCG_ERR_BREAKDOWN, MSPCG_ERR_OOM):
+            _check(st)
+        return st, [_stats(a.status, a) for a in arr], lat.value
+
+    def info(self):
+        i = mspcg_server_stats()
+        _check(mspcg_server_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in mspcg_server_stats._fields_}

@@ -45,6 +45,13 @@ template <typename S> struct Field {
   chunk* data;     // nchunk arrays of `stride` chunks
   float* scale;    // 16-bit formats only
   int64_t stride;
+  // right-hand side r of a batch stored one whole field after another
+  __device__ __forceinline__ Field at(int r) const {
+    Field f = *this;
+    if (data) f.data += (int64_t)r * StoreTraits<S>::nchunk * stride;
+    if (scale) f.scale += (int64_t)r * stride;
+    return f;
+  }
 };
 
 // 16-bit values are taken from and put into 32-bit words with shifts only:

@@ -6,12 +6,15 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
+#include "internal.h"
 #include "kernels.h"
 #include "mspcg.h"
 
@@ -68,6 +71,8 @@ Prec to_prec(mspcg_prec p) {
   }
   throw Error(MSPCG_ERR_INVALID_ARG, "unknown precision");
 }
+
+int64_t round16(int64_t b) { return (b + 15) / 16 * 16; }
 
 size_t chunk_bytes(Prec p) { return p == Prec::F64 ? 192 : p == Prec::F32 ? 96 : 48; }
 
@@ -255,6 +260,8 @@ struct EventPair {
 
 }  // namespace
 
+void mspcg::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
 // ==========================================================================
 // the handle
 // ==========================================================================
@@ -265,7 +272,11 @@ struct mspcg_ctx {
   bool hip_ready = false;
   hipStream_t stream = nullptr;
 
-  DevBuf gauge64, gauge32;
+  // device links, FP64 and FP32 layouts; shared between handles on one field
+  struct GaugeStore {
+    DevBuf g64, g32;
+  };
+  std::shared_ptr<GaugeStore> gs;
   bool have_gauge = false;
 
   int Ls = 0;
@@ -284,6 +295,7 @@ struct mspcg_ctx {
 
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   double* h_scal = nullptr;   // pinned
+  int* h_flag = nullptr;      // pinned: RHS still active, one slot per graph replay in flight
 
   bool profiling = false;
   std::vector<EventPair> ev_pool;
@@ -313,6 +325,7 @@ struct mspcg_ctx {
       }
       ws.clear();
       if (h_scal) (void)hipHostFree(h_scal);
+      if (h_flag) (void)hipHostFree(h_flag);
       (void)hipStreamDestroy(stream);
     }
   }
@@ -322,6 +335,7 @@ struct mspcg_ctx {
     if (hip_ready) return;
     HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void**)&h_scal, SLOT_COUNT * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h_flag, 4 * sizeof(int), hipHostMallocDefault));
     hip_ready = true;
   }
 
@@ -334,14 +348,16 @@ struct mspcg_ctx {
 
   int64_t n5() const { return lat.vh * Ls; }
 
-  FieldPtr field(const std::string& key, Prec p, int64_t nsites) {
+  // a field of nsites 4D sites (x Ls), nb right-hand sides one after another
+  FieldPtr field(const std::string& key, Prec p, int64_t nsites, int nb = 1) {
     const int64_t n = nsites * Ls;
     FieldPtr f;
     f.prec = p;
     f.stride = n;
-    DevBuf& d = buf(key, (size_t)n * chunk_bytes(p));
+    DevBuf& d = buf(key, (size_t)nb * n * chunk_bytes(p));
     f.data = d.p;
-    if (p == Prec::F16 || p == Prec::BF16) f.scale = buf(key + ".scale", (size_t)n * sizeof(float)).as<float>();
+    if (p == Prec::F16 || p == Prec::BF16)
+      f.scale = buf(key + ".scale", (size_t)round16((int64_t)nb * n * sizeof(float))).as<float>();
     return f;
   }
 
@@ -350,10 +366,36 @@ struct mspcg_ctx {
     if (p == Prec::F64) return mats64.as<double>() + off;
     return mats32.as<float>() + off;
   }
-  const void* gauge(Prec p) const { return p == Prec::F64 ? gauge64.p : gauge32.p; }
+  const void* gauge(Prec p) const { return p == Prec::F64 ? gs->g64.p : gs->g32.p; }
+
+  // bytes of the workspaces, matrices and tables this handle holds (not the
+  // gauge field)
+  int64_t ws_bytes() const {
+    int64_t n = (int64_t)mats64.n + (int64_t)mats32.n;
+    for (const DevBuf* d : {&tb_origin, &tb_cC, &tb_cN1, &tb_cN2, &tb_nbr1, &tb_nbr2, &tb_nbr3, &tb_nbr4, &tb_w2, &tb_w4})
+      n += (int64_t)d->n;
+    for (auto& kv : ws) n += kv.second ? (int64_t)kv.second->n : 0;
+    return n;
+  }
 
   double* partial(const std::string& key, int64_t n) { return buf("partial." + key, (size_t)n * sizeof(double)).as<double>(); }
-  double* scal() { return buf("scalars", SLOT_COUNT * sizeof(double)).as<double>(); }
+  double* scal(int nb = 1) { return buf("scalars", (size_t)nb * SLOT_COUNT * sizeof(double)).as<double>(); }
+
+  // ---------------------------------------------------------------- launch schedules
+  // Tuned workgroup schedules of the hop kernels, per (hop kind, precision,
+  // number of RHS); kinds: 0 full-lattice hops of the outer precision,
+  // 1 FP64 hops, 2 subdomain hops.  Untuned: one workgroup per item, RHS of
+  // one site block adjacent.
+  std::map<std::tuple<int, int, int>, Sched> tuned;
+  std::map<std::tuple<int, int, int>, double> tuned_us;
+  Sched sched(int kind, Prec p, int nrhs) const {
+    auto it = tuned.find(std::make_tuple(kind, (int)p, nrhs));
+    if (it != tuned.end()) return it->second;
+    Sched sc;
+    sc.order = nrhs > 1 ? 1 : 0;
+    sc.xcd = 1;
+    return sc;
+  }
 
   void invalidate_workspace() {
     if (hip_ready) HIPCHK(hipStreamSynchronize(stream));
@@ -415,13 +457,13 @@ struct mspcg_ctx {
   // stage: 1..4 for the four hops of A (0 for other uses); profiling kind
   // 20 + stage (FP32/16-bit) or 30 + stage (FP64)
   void hop(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int out_par, bool dag,
-           const Epilogue& epi, int stage = 0) {
+           const Epilogue& epi, int stage = 0, const Batch& bt = Batch()) {
     HopGeometry g;
     g.lat = lat;
     g.out_parity = out_par;
     g.Ls = Ls;
     const size_t e = ev_begin(st, (p == Prec::F64 ? 30 : 20) + stage);
-    hop_full(st, p, out, in, w, gauge(p), g, dag, epi);
+    hop_full(st, p, out, in, w, gauge(p), g, dag, epi, bt, sched(p == Prec::F64 ? 1 : 0, p, bt.n));
     ev_end(st, e);
   }
 
@@ -440,19 +482,20 @@ struct mspcg_ctx {
   //   e = Q^dag D^w^dag c,  out = M5^dag c - M_phi^dag D^w^dag e  (= D^dag D p).
   // dot_partial gets <p, A p> per block of the last hop.
   void A_from_t0(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr& t0,
-                 const std::string& tag, double* dot_partial) {
-    FieldPtr a = field(tag + ".a", p, lat.vh), c = field(tag + ".c", p, lat.vh), e = field(tag + ".e", p, lat.vh);
-    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q), 1);
-    hop(st, p, c, a, &in, 0, false, epi(p, MAT_M5INV_T, MAT_NEG_M5INVT_M5INV), 2);
-    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT), 3);
-    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, false, dot_partial, &in), 4);
+                 const std::string& tag, double* dot_partial, const Batch& bt = Batch()) {
+    FieldPtr a = field(tag + ".a", p, lat.vh, bt.n), c = field(tag + ".c", p, lat.vh, bt.n),
+             e = field(tag + ".e", p, lat.vh, bt.n);
+    hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q), 1, bt);
+    hop(st, p, c, a, &in, 0, false, epi(p, MAT_M5INV_T, MAT_NEG_M5INVT_M5INV), 2, bt);
+    hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT), 3, bt);
+    hop(st, p, out, e, &c, 0, true, epi(p, MAT_M5_T, MAT_NEG_MPHI_T, false, dot_partial, &in), 4, bt);
   }
 
   void A_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag,
-            double* norm_partial) {
-    FieldPtr t0 = field(tag + ".t0", p, lat.vh);
-    apply5_full(st, p, t0, in, mat(p, MAT_MPHI), lat.vh, Ls, nullptr);
-    A_from_t0(st, p, out, in, t0, tag, norm_partial);
+            double* norm_partial, const Batch& bt = Batch()) {
+    FieldPtr t0 = field(tag + ".t0", p, lat.vh, bt.n);
+    apply5_full(st, p, t0, in, mat(p, MAT_MPHI), lat.vh, Ls, nullptr, bt);
+    A_from_t0(st, p, out, in, t0, tag, norm_partial, bt);
   }
 
   void D_op(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const std::string& tag) {
@@ -471,13 +514,15 @@ struct mspcg_ctx {
 
   // A_s p_s for every subdomain (inner storage I), given t0 = M_phi p_s on C.
   // <p_s, A_s p_s> partials [d][bps of C] when dot != null.
-  void Asub(hipStream_t st, Prec I, const FieldPtr& q, const FieldPtr& ps, const FieldPtr& t0, double* dot) {
-    FieldPtr a = field("in.a", I, (int64_t)nsub * nN1), c = field("in.c", I, (int64_t)nsub * nN2),
-             e = field("in.e", I, (int64_t)nsub * nN1);
+  void Asub(hipStream_t st, Prec I, const FieldPtr& q, const FieldPtr& ps, const FieldPtr& t0, double* dot,
+            const Batch& bt = Batch()) {
+    FieldPtr a = field("in.a", I, (int64_t)nsub * nN1, bt.n), c = field("in.c", I, (int64_t)nsub * nN2, bt.n),
+             e = field("in.e", I, (int64_t)nsub * nN1, bt.n);
+    const Sched sc = sched(2, I, bt.n);
     auto run = [&](int which, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int par, bool dag,
                    const Epilogue& E) {
       const size_t ev = ev_begin(st, 10 + which);
-      hop_sub(st, I, out, in, w, gauge(I), lat, par, tables(which, I), nsub, Ls, dag, E);
+      hop_sub(st, I, out, in, w, gauge(I), lat, par, tables(which, I), nsub, Ls, dag, E, bt, sc);
       ev_end(st, ev);
     };
     run(1, a, t0, nullptr, 1, false, epi(I, -1, MAT_Q));
@@ -489,29 +534,30 @@ struct mspcg_ctx {
   // z = (+)_s CG_k(A_s, R_s r).  Outer precision O for r, z, r_old.
   // dots: partials of <z, r> and <z, r_old> into pz1/pz2 (nsub * bpsC entries).
   int precondition(hipStream_t st, Prec O, Prec I, const FieldPtr& z, const FieldPtr& r, const FieldPtr* rold,
-                   int k, double* pz1, double* pz2) {
+                   int k, double* pz1, double* pz2, const Batch& bt = Batch()) {
     const size_t ev = ev_begin(st, 2);
     const int64_t nc = (int64_t)nsub * nC;
-    FieldPtr rs = field("in.r", I, nc), ps = field("in.p", I, nc), zs = field("in.z", I, nc),
-             qs = field("in.q", I, nc), t0 = field("in.t0", I, nc);
+    const int nb = bt.n;
+    FieldPtr rs = field("in.r", I, nc, nb), ps = field("in.p", I, nc, nb), zs = field("in.z", I, nc, nb),
+             qs = field("in.q", I, nc, nb), t0 = field("in.t0", I, nc, nb);
     SubScalars sc;
-    sc.rho = buf("in.rho", nsub * sizeof(double)).as<double>();
-    sc.alpha = buf("in.alpha", nsub * sizeof(double)).as<double>();
-    sc.beta = buf("in.beta", nsub * sizeof(double)).as<double>();
-    sc.active = buf("in.active", nsub * sizeof(int)).as<int>();
+    sc.rho = buf("in.rho", (size_t)nb * nsub * sizeof(double)).as<double>();
+    sc.alpha = buf("in.alpha", (size_t)nb * nsub * sizeof(double)).as<double>();
+    sc.beta = buf("in.beta", (size_t)nb * nsub * sizeof(double)).as<double>();
+    sc.active = buf("in.active", (size_t)nb * nsub * sizeof(int)).as<int>();
     const SubTables tc = tables(0, I);
-    double* prr = partial("in.rr", (int64_t)nsub * tc.bps);
-    double* ppap = partial("in.pap", (int64_t)nsub * tc.bps);
-    sub_restrict(st, O, I, r, rs, ps, t0, mat(I, MAT_MPHI), lat, tc, nsub, Ls, prr);
-    sub_finish(st, prr, tc.bps, nsub, sc, SUB_INIT);
+    double* prr = partial("in.rr", (int64_t)nb * nsub * tc.bps);
+    double* ppap = partial("in.pap", (int64_t)nb * nsub * tc.bps);
+    sub_restrict(st, O, I, r, rs, ps, t0, mat(I, MAT_MPHI), lat, tc, nsub, Ls, prr, bt);
+    sub_finish(st, prr, tc.bps, nsub, sc, SUB_INIT, bt);
     for (int it = 0; it < k; ++it) {
-      if (it > 0) sub_xpay5(st, I, ps, rs, t0, sc, mat(I, MAT_MPHI), tc, nsub, Ls);
-      Asub(st, I, qs, ps, t0, ppap);
-      sub_finish(st, ppap, tc.bps, nsub, sc, SUB_ALPHA);
-      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, prr);
-      sub_finish(st, prr, tc.bps, nsub, sc, SUB_BETA);
+      if (it > 0) sub_xpay5(st, I, ps, rs, t0, sc, mat(I, MAT_MPHI), tc, nsub, Ls, bt);
+      Asub(st, I, qs, ps, t0, ppap, bt);
+      sub_finish(st, ppap, tc.bps, nsub, sc, SUB_ALPHA, bt);
+      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, prr, bt);
+      sub_finish(st, prr, tc.bps, nsub, sc, SUB_BETA, bt);
     }
-    sub_prolong(st, O, I, z, zs, r, rold, lat, tc, nsub, Ls, pz1, pz2);
+    sub_prolong(st, O, I, z, zs, r, rold, lat, tc, nsub, Ls, pz1, pz2, bt);
     ev_end(st, ev);
     return k;
   }
@@ -695,6 +741,7 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
     }
     S.true_rel_resid = std::sqrt(std::fabs(rr)) / bnorm;
   }
+  S.status = status;
   unpack_field(st, x_dev, x64, vh, Ls);
   HIPCHK(hipEventRecord(e1, st));
   HIPCHK(hipEventSynchronize(e1));
@@ -714,6 +761,390 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
   }
   if (stats) *stats = S;
   return status;
+}
+
+// --------------------------------------------------------------------------
+// Batched solve: nrhs right-hand sides on one gauge field, every kernel of
+// an iteration launched once for all of them.  The iteration's decisions are
+// taken on the device (ctl_*), masks drop finished RHS from every launch, and
+// two iterations (one period of the r / r_old ping-pong) are captured in a
+// graph that is replayed until no RHS is active.  The arithmetic of every RHS
+// is that of the single-RHS solve: the same kernels, block partitions and
+// reduction orders, with the same decisions taken in the same order.
+// --------------------------------------------------------------------------
+struct GraphGuard {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  ~GraphGuard() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
+mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, double* x_dev, const double* x0_dev,
+                              hipStream_t st, mspcg_stats* stats) {
+  const mspcg_solver_params& sp = h->sp;
+  const Prec O = to_prec(sp.outer_prec);
+  const Prec I = to_prec(sp.inner_prec);
+  const bool pre = sp.use_precond != 0;
+  const bool pr = sp.beta_rule == 0;
+  const int64_t vh = h->lat.vh, n5 = h->n5(), nreal = n5 * 24;
+  const int Ls = h->Ls;
+  const int n = nrhs;
+  if (pre && !h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "MSPCG needs mspcg_set_subdomains");
+  if (pre && sp.inner_iters < 1) throw Error(MSPCG_ERR_INVALID_ARG, "MSPCG needs inner_iters >= 1");
+  const bool use_graph = !h->profiling;
+
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, st));
+
+  double* scal = h->scal(n);
+  const int64_t nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4));
+  const int64_t nbl64 = blas_blocks(nreal / 2);
+  double* p_upd = h->partial("upd", nbl * n);
+  double* p_ru = h->partial("ru", nbl64 * n);
+  double* p_b = h->partial("b", nbl64 * n);
+  const int64_t bps_hop = full_blocks(vh, Ls, O);
+  double* p_pap = h->partial("pap", bps_hop * n);
+  int64_t nz = nbl;
+  if (pre) nz = (int64_t)h->nsub * h->tables(0, I).bps;
+  double* p_z1 = h->partial("z1", nz * n);
+  double* p_z2 = h->partial("z2", nz * n);
+
+  // per-RHS control state
+  int* ci = h->buf("ctl.i", (size_t)(8 * n + 1) * sizeof(int)).as<int>();
+  double* cd = h->buf("ctl.d", (size_t)3 * n * sizeof(double)).as<double>();
+  Ctl c;
+  c.active = ci;
+  c.ru = ci + n;
+  c.bzero = ci + 2 * n;
+  c.status = ci + 3 * n;
+  c.iters = ci + 4 * n;
+  c.rus = ci + 5 * n;
+  c.precs = ci + 6 * n;
+  c.nactive = ci + 8 * n;
+  c.bnorm = cd;
+  c.rmax = cd + n;
+  c.rr = cd + 2 * n;
+  CtlParams cp;
+  cp.tol = sp.tol;
+  cp.delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.0;
+  cp.maxiter = sp.maxiter;
+  Batch all, act, rum, bz;
+  all.n = act.n = rum.n = bz.n = n;
+  act.mask = c.active;
+  rum.mask = c.ru;
+  bz.mask = c.bzero;
+
+  FieldPtr b64 = h->field("s.b64", Prec::F64, vh, n), x64 = h->field("s.x64", Prec::F64, vh, n);
+  FieldPtr q64 = h->field("s.q64", Prec::F64, vh, n);
+  FieldPtr r64 = O == Prec::F64 ? FieldPtr() : h->field("s.r64", Prec::F64, vh, n);
+  FieldPtr x = O == Prec::F64 ? x64 : h->field("s.x", O, vh, n);
+  FieldPtr rA = h->field("s.rA", O, vh, n), rB = h->field("s.rB", O, vh, n);
+  FieldPtr z = pre ? h->field("s.z", O, vh, n) : rA;
+  FieldPtr p = h->field("s.p", O, vh, n), q = h->field("s.q", O, vh, n), t0 = h->field("s.t0", O, vh, n);
+  const int64_t bytes64 = n5 * 192, bytesO = n5 * (int64_t)chunk_bytes(O);
+
+  pack_field(st, b64, b_dev, vh, Ls, all);
+  if (x0_dev) pack_field(st, x64, x0_dev, vh, Ls, all);
+  else zero_batched(st, x64.data, bytes64, all);
+  if (O == Prec::F32) zero_batched(st, x.data, bytesO, all);
+  zero_batched(st, p.data, bytesO, all);
+
+  dot2(st, Prec::F64, b64.data, b64.data, nullptr, nreal, p_b, nullptr, nbl64, all);
+  finish(st, p_b, nullptr, nbl64, scal, FIN_STORE, SLOT_TMP, all);
+  ctl_init(st, c, scal, n);
+  zero_batched(st, x64.data, bytes64, bz);
+
+  FieldPtr* r = &rA;
+  FieldPtr* rold = &rB;
+  // r = b - A x (FP64) for the masked RHS; lower-precision copy into *r
+  auto true_residual = [&](const Batch& m) {
+    h->A_op(st, Prec::F64, q64, x64, "A64", nullptr, m);
+    residual64(st, (const double*)b64.data, (const double*)q64.data,
+               O == Prec::F64 ? (double*)r->data : (double*)r64.data, O == Prec::F32 ? (float*)r->data : nullptr,
+               n5, p_ru, nbl64, m);
+    finish(st, p_ru, nullptr, nbl64, scal, FIN_STORE, SLOT_R64, m);
+  };
+  if (x0_dev) true_residual(act);
+  else if (O == Prec::F32) f64_to_f32(st, (const double*)b64.data, (float*)r->data, n5, act);
+  else apply5_full(st, Prec::F64, *r, b64, nullptr, vh, Ls, nullptr, act);
+  ctl_start(st, c, scal, n, x0_dev != nullptr);
+
+  // z = M r ; rho = <r, z> ; p = z ; t0 = M_phi p
+  if (pre) {
+    h->precondition(st, O, I, z, *r, nullptr, sp.inner_iters, p_z1, p_z2, act);
+    finish(st, p_z1, nullptr, nz, scal, FIN_RHO, 0, act);
+  } else {
+    dot2(st, O, r->data, r->data, nullptr, nreal, p_z1, nullptr, nbl, act);
+    finish(st, p_z1, nullptr, nbl, scal, FIN_RHO, 0, act);
+  }
+  xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_TMP, h->mat(O, MAT_MPHI), vh, Ls, act);
+
+  auto iteration = [&]() {
+    h->A_from_t0(st, O, q, p, t0, "Aout", p_pap, act);
+    finish(st, p_pap, nullptr, bps_hop, scal, FIN_ALPHA, 0, act);
+    cg_update(st, O, x.data, p.data, r->data, q.data, rold->data, nreal, scal, SLOT_ALPHA, p_upd, nbl, act);
+    std::swap(r, rold);
+    finish(st, p_upd, nullptr, nbl, scal, FIN_STORE, SLOT_RR, act);
+    ctl_iterate(st, c, scal, n, cp);
+    if (O == Prec::F32) accum_lo(st, (double*)x64.data, (float*)x.data, n5, rum);
+    true_residual(rum);
+    ctl_after_update(st, c, scal, n, cp);
+    if (pre) {
+      h->precondition(st, O, I, z, *r, pr ? rold : nullptr, sp.inner_iters, p_z1, p_z2, act);
+      finish(st, p_z1, pr ? p_z2 : nullptr, nz, scal, pr ? FIN_BETA_PR : FIN_BETA_FR, 0, act);
+    } else if (pr) {
+      dot2(st, O, r->data, r->data, rold->data, nreal, p_z1, p_z2, nbl, act);
+      finish(st, p_z1, p_z2, nbl, scal, FIN_BETA_PR, 0, act);
+    } else {
+      finish(st, nullptr, nullptr, 0, scal, FIN_BETA_FR, SLOT_RR, act);
+    }
+    xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_BETA, h->mat(O, MAT_MPHI), vh, Ls, act);
+  };
+  auto body = [&]() {
+    iteration();
+    iteration();
+  };
+
+  // the first pair runs eagerly (it sizes every workspace), then the pair is
+  // captured once and replayed; the host reads the active count of replay k
+  // while replay k + 1 runs
+  int64_t launched = 0;
+  const int64_t limit = (int64_t)sp.maxiter + 8;
+  auto post_flag = [&](int slot) {
+    HIPCHK(hipMemcpyAsync(h->h_flag + slot, c.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+  };
+  hipEvent_t fev[2];
+  HIPCHK(hipEventCreateWithFlags(&fev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&fev[1], hipEventDisableTiming));
+  GraphGuard gg;
+  try {
+    body();
+    launched += 2;
+    post_flag(0);
+    HIPCHK(hipStreamSynchronize(st));
+    if (h->h_flag[0] > 0) {
+      if (use_graph) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+          body();
+        } catch (...) {
+          hipGraph_t junk = nullptr;
+          (void)hipStreamEndCapture(st, &junk);
+          if (junk) (void)hipGraphDestroy(junk);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(st, &gg.g));
+        HIPCHK(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+      }
+      for (int64_t k = 0;; ++k) {
+        if (use_graph) HIPCHK(hipGraphLaunch(gg.e, st));
+        else body();
+        launched += 2;
+        post_flag((int)(k & 1));
+        HIPCHK(hipEventRecord(fev[k & 1], st));
+        if (k > 0) {
+          HIPCHK(hipEventSynchronize(fev[(k - 1) & 1]));
+          if (h->h_flag[(k - 1) & 1] == 0) break;
+        }
+        if (launched > limit) {
+          HIPCHK(hipEventSynchronize(fev[k & 1]));
+          if (h->h_flag[k & 1] == 0) break;
+          throw Error(MSPCG_ERR_HIP, "batched solve did not stop at the iteration limit");
+        }
+      }
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(fev[0]);
+    (void)hipEventDestroy(fev[1]);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(fev[0]);
+  (void)hipEventDestroy(fev[1]);
+
+  unpack_field(st, x_dev, x64, vh, Ls, all);
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+
+  std::vector<int> hi((size_t)8 * n + 1);
+  std::vector<double> hd((size_t)3 * n);
+  HIPCHK(hipMemcpy(hi.data(), ci, hi.size() * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(hd.data(), cd, hd.size() * sizeof(double), hipMemcpyDeviceToHost));
+  double ms_pre = 0;
+  if (h->profiling) {
+    for (auto& kv : h->ev_log)
+      if (kv.first == 2) {
+        float m = 0;
+        if (hipEventElapsedTime(&m, h->ev_pool[kv.second].a, h->ev_pool[kv.second].b) == hipSuccess) ms_pre += m;
+      }
+  }
+  bool any_nc = false, any_bd = false;
+  for (int i = 0; i < n; ++i) {
+    const int status = hi[3 * n + i];
+    any_bd |= status == RHS_BREAKDOWN;
+    any_nc |= status == RHS_NOT_CONVERGED || status == RHS_RUNNING;
+    if (!stats) continue;
+    mspcg_stats& S = stats[i];
+    std::memset(&S, 0, sizeof(S));
+    S.outer_iters = hi[4 * n + i];
+    S.reliable_updates = hi[5 * n + i];
+    S.inner_iters_total = pre ? hi[6 * n + i] * sp.inner_iters : 0;
+    const double bn = hd[i], rr = hd[2 * n + i];
+    const double rel = (hi[2 * n + i] || !(bn > 0)) ? 0.0 : std::sqrt(std::fabs(rr)) / bn;
+    S.true_rel_resid = rel;
+    S.iter_rel_resid = rel;
+    S.ms_total = ms;
+    S.ms_precond = ms_pre;
+    S.status = status == RHS_OK ? MSPCG_OK
+               : status == RHS_BREAKDOWN ? MSPCG_ERR_BREAKDOWN
+                                         : MSPCG_NOT_CONVERGED;
+  }
+  if (any_bd) return MSPCG_ERR_BREAKDOWN;
+  return any_nc ? MSPCG_NOT_CONVERGED : MSPCG_OK;
+}
+
+// --------------------------------------------------------------------------
+// Autotuner of the hop schedules: time the four hops of one A application
+// (outer precision, FP64) and of one A_s application (inner precision) for
+// nrhs right-hand sides under every candidate schedule; keep the fastest.
+// --------------------------------------------------------------------------
+void autotune_impl(mspcg_ctx* h, int nrhs, hipStream_t st) {
+  std::vector<Sched> cand;
+  for (int order = 0; order < (nrhs > 1 ? 2 : 1); ++order)
+    for (int xcd = 0; xcd < 2; ++xcd) {
+      Sched sc;
+      sc.order = order;
+      sc.xcd = xcd;
+      cand.push_back(sc);
+    }
+  const Prec O = to_prec(h->sp.outer_prec), I = to_prec(h->sp.inner_prec);
+  const int64_t vh = h->lat.vh;
+  Batch bt;
+  bt.n = nrhs;
+  hipEvent_t ea, eb;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  const bool prof = h->profiling;
+  h->profiling = false;
+  struct Kind {
+    int kind;
+    Prec p;
+  };
+  std::vector<Kind> kinds;
+  kinds.push_back({O == Prec::F64 ? 1 : 0, O});
+  if (O != Prec::F64) kinds.push_back({1, Prec::F64});
+  if (h->have_tiling) kinds.push_back({2, I});
+  try {
+    for (const Kind& k : kinds) {
+      std::function<void()> run;
+      FieldPtr in, out, t0;
+      if (k.kind == 2) {
+        const int64_t nc = (int64_t)h->nsub * h->nC;
+        in = h->field("tune.in", k.p, nc, nrhs);
+        out = h->field("tune.out", k.p, nc, nrhs);
+        t0 = h->field("tune.t0", k.p, nc, nrhs);
+        run = [&]() { h->Asub(st, k.p, out, in, t0, nullptr, bt); };
+      } else {
+        in = h->field("tune.in", k.p, vh, nrhs);
+        out = h->field("tune.out", k.p, vh, nrhs);
+        t0 = h->field("tune.t0", k.p, vh, nrhs);
+        run = [&]() { h->A_from_t0(st, k.p, out, in, t0, "tune", nullptr, bt); };
+      }
+      const int64_t bytes = in.stride * (int64_t)chunk_bytes(k.p);
+      zero_batched(st, in.data, bytes, bt);
+      zero_batched(st, t0.data, bytes, bt);
+      if (in.scale) {
+        zero_batched(st, in.scale, round16((int64_t)nrhs * in.stride * 4), Batch());
+        zero_batched(st, t0.scale, round16((int64_t)nrhs * t0.stride * 4), Batch());
+      }
+      const auto key = std::make_tuple(k.kind, (int)k.p, nrhs);
+      double best = 1e30;
+      Sched bsc;
+      for (const Sched& sc : cand) {
+        h->tuned[key] = sc;
+        run();   // warm
+        HIPCHK(hipEventRecord(ea, st));
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r) run();
+        HIPCHK(hipEventRecord(eb, st));
+        HIPCHK(hipEventSynchronize(eb));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ea, eb));
+        const double us = 1e3 * ms / reps;
+        if (us < best) {
+          best = us;
+          bsc = sc;
+        }
+      }
+      h->tuned[key] = bsc;
+      h->tuned_us[key] = best;
+    }
+  } catch (...) {
+    h->profiling = prof;
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    throw;
+  }
+  h->profiling = prof;
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  for (auto it = h->ws.begin(); it != h->ws.end();) {
+    if (it->first.compare(0, 5, "tune.") == 0) it = h->ws.erase(it);
+    else ++it;
+  }
+}
+
+// Device bytes of the workspaces a batched solve of nrhs right-hand sides
+// allocates (the fields and partial arrays of solve_batch_impl, the operator
+// chains and the preconditioner), plus the matrices and tables.
+int64_t estimate_solve_bytes(const mspcg_ctx* h, int nrhs) {
+  const mspcg_solver_params& sp = h->sp;
+  const Prec O = to_prec(sp.outer_prec), I = to_prec(sp.inner_prec);
+  const bool pre = sp.use_precond != 0;
+  const int64_t vh = h->lat.vh, n5 = h->n5(), nreal = n5 * 24;
+  const int Ls = h->Ls;
+  auto fbytes = [&](Prec p, int64_t sites5) {
+    int64_t b = sites5 * (int64_t)chunk_bytes(p);
+    if (p == Prec::F16 || p == Prec::BF16) b += round16(sites5 * 4);
+    return b;
+  };
+  int64_t n = 0;
+  // FP64: b, x, A x, the A64 chain (t0, a, c, e), r64 with an FP32 outer solve
+  n += (7 + (O == Prec::F32 ? 1 : 0)) * fbytes(Prec::F64, n5);
+  // outer vectors: x (FP32), r, r_old, z, p, q, t0 and the A chain (a, c, e)
+  const int nO = (O == Prec::F32 ? 1 : 0) + 2 + (pre ? 1 : 0) + 3 + 3;
+  n += nO * fbytes(O, n5);
+  const int64_t nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4)), nbl64 = blas_blocks(nreal / 2);
+  int64_t parts = nbl + 2 * nbl64 + full_blocks(vh, Ls, O);
+  if (pre && h->have_tiling) {
+    const int64_t bps = (h->nC + sites_per_block(Ls, I) - 1) / sites_per_block(Ls, I);
+    const int64_t nc5 = (int64_t)h->nsub * h->nC * Ls;
+    n += 5 * fbytes(I, nc5);
+    n += 2 * fbytes(I, (int64_t)h->nsub * h->nN1 * Ls) + fbytes(I, (int64_t)h->nsub * h->nN2 * Ls);
+    parts += 4 * (int64_t)h->nsub * bps;
+    n += (int64_t)h->nsub * (3 * 8 + 4);
+  } else {
+    parts += 2 * nbl;
+  }
+  n += parts * 8;
+  n *= nrhs;
+  n += (int64_t)(8 * nrhs + 1) * 4 + (int64_t)3 * nrhs * 8 + (int64_t)nrhs * SLOT_COUNT * 8;
+  // matrices and tables
+  n += (int64_t)h->mats64.n + (int64_t)h->mats32.n;
+  for (const DevBuf* d : {&h->tb_origin, &h->tb_cC, &h->tb_cN1, &h->tb_cN2, &h->tb_nbr1, &h->tb_nbr2, &h->tb_nbr3,
+                          &h->tb_nbr4, &h->tb_w2, &h->tb_w4})
+    n += (int64_t)d->n;
+  return n;
 }
 
 void apply_impl(mspcg_ctx* h, int op, Prec P, const double* in_dev, double* out_dev, hipStream_t st) {
@@ -818,10 +1249,12 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
     DevBuf stage;
     stage.ensure(canon);
     HIPCHK(hipMemcpyAsync(stage.p, U, canon, hipMemcpyHostToDevice, st));
-    h->gauge64.ensure((size_t)V * 4 * 9 * sizeof(double2));
-    h->gauge32.ensure((size_t)V * 4 * 9 * sizeof(float2));
-    pack_gauge(st, h->gauge64.p, true, stage.as<double>(), h->lat);
-    pack_gauge(st, h->gauge32.p, false, stage.as<double>(), h->lat);
+    auto g = std::make_shared<mspcg_ctx::GaugeStore>();
+    g->g64.ensure((size_t)V * 4 * 9 * sizeof(double2));
+    g->g32.ensure((size_t)V * 4 * 9 * sizeof(float2));
+    pack_gauge(st, g->g64.p, true, stage.as<double>(), h->lat);
+    pack_gauge(st, g->g32.p, false, stage.as<double>(), h->lat);
+    h->gs = g;
     HIPCHK(hipStreamSynchronize(st));
     h->have_gauge = true;
     return MSPCG_OK;
@@ -842,6 +1275,8 @@ mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double 
     h->mats32.ensure(m32.size() * sizeof(float));
     HIPCHK(hipMemcpy(h->mats64.p, M.m.data(), M.m.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(h->mats32.p, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice));
+    h->tuned.clear();
+    h->tuned_us.clear();
     h->Ls = Ls;
     h->b = b;
     h->c = c;
@@ -893,6 +1328,8 @@ mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
       h->nsub *= h->nblk[m];
     }
     h->have_tiling = true;
+    h->tuned.clear();
+    h->tuned_us.clear();
     return MSPCG_OK;
   });
 }
@@ -942,6 +1379,70 @@ mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0
     HIPCHK(hipMemcpyAsync(x, dx.p, bytes, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return r;
+  });
+}
+
+mspcg_status mspcg_solve_batch_device(mspcg_t h, int32_t nrhs, const double* b, double* x, const double* x0,
+                                      void* hip_stream, mspcg_stats* st) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
+    need_state(h);
+    h->ensure_hip();
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
+    return solve_batch_impl(h, nrhs, b, x, x0, s, st);
+  });
+}
+
+mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !src) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (!src->have_gauge) throw Error(MSPCG_ERR_NO_GAUGE, "source handle has no gauge field");
+    for (int m = 0; m < 4; ++m)
+      if (h->dims[m] != src->dims[m]) throw Error(MSPCG_ERR_INVALID_ARG, "lattice extents differ");
+    if (h->device != src->device) throw Error(MSPCG_ERR_INVALID_ARG, "handles are on different devices");
+    h->ensure_hip();
+    h->gs = src->gs;
+    h->have_gauge = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_footprint(mspcg_t h, int32_t nrhs, int64_t* estimate, int64_t* allocated) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !estimate || !allocated) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
+    if (!h->have_params) throw Error(MSPCG_ERR_NO_PARAMS, "Mobius parameters not set");
+    *estimate = estimate_solve_bytes(h, nrhs);
+    *allocated = h->ws_bytes();
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_autotune(mspcg_t h, int32_t nrhs) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
+    need_state(h);
+    h->ensure_hip();
+    autotune_impl(h, nrhs, h->stream);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_get_schedule(mspcg_t h, int32_t kind, int32_t nrhs, int32_t* order, int32_t* xcd, double* us) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !order || !xcd || !us) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (kind < 0 || kind > 2) throw Error(MSPCG_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+    const Prec p = kind == 1 ? Prec::F64 : to_prec(kind == 0 ? h->sp.outer_prec : h->sp.inner_prec);
+    const int k = (kind == 0 && p == Prec::F64) ? 1 : kind;
+    const Sched sc = h->sched(k, p, nrhs);
+    *order = sc.order;
+    *xcd = sc.xcd;
+    auto it = h->tuned_us.find(std::make_tuple(k, (int)p, nrhs));
+    *us = it == h->tuned_us.end() ? 0.0 : it->second;
+    return MSPCG_OK;
   });
 }
 

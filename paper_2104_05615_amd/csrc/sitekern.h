@@ -327,10 +327,29 @@ inline size_t site_lds_bytes(int ns, int Ls, bool tileB, bool mfma) {
 // a field read at the output site).  MF selects the MFMA epilogue (ns = 16).
 //
 // Occupancy floor: the hop is latency bound on its neighbour loads.
+// (site block, RHS) work items of one hop launch, one per workgroup
+struct HopWork {
+  int64_t nblk;      // site blocks per RHS
+  int nrhs;
+  int order;         // 0: item = rhs * nblk + blk; 1: item = blk * nrhs + rhs
+  int xcd;           // 1: items dealt to XCDs in contiguous ranges (xcd_block)
+  const int* mask;   // RHS r skipped when mask[r] == 0 (nullable)
+  __device__ __forceinline__ void decode(int64_t b, int64_t nb, int64_t& blk, int& rhs) const {
+    const int64_t item = xcd ? xcd_block(b, nb) : b;
+    if (order == 0) {
+      rhs = (int)(item / nblk);
+      blk = item - (int64_t)rhs * nblk;
+    } else {
+      blk = item / nrhs;
+      rhs = (int)(item - blk * nrhs);
+    }
+  }
+};
+
 template <typename Geo, typename S, bool DAG, bool HASW, bool MF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(calc_t<S>) == 8 ? 2 : 4)))
-k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, Field<S> dotf, int Ls, int ns, const calc_t<S>* E0,
-      const calc_t<S>* E1, int w_identity, double* dot_partial) {
+k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int Ls, int ns, const calc_t<S>* E0,
+      const calc_t<S>* E1, int w_identity, double* dot_partial, HopWork wk) {
   using T = calc_t<S>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* red = reinterpret_cast<double*>(lds_raw);
@@ -344,9 +363,6 @@ k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, Field<S> dotf, int Ls, int
   const int tid = threadIdx.x;
   const bool inb = tid < ns * Ls;
   const int sl = inb ? tid / Ls : 0, s = inb ? tid - sl * Ls : 0;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const SiteRef r = geo.locate(blk, sl, ns, Ls, s);
-  const bool valid = inb && r.valid;
 
   if constexpr (!MF) {
     const int nm = 2 * Ls * Ls;
@@ -355,6 +371,14 @@ k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, Field<S> dotf, int Ls, int
       if (E1) mats[nm + k] = E1[k];
     }
   }
+
+  int64_t blk;
+  int rhs;
+  wk.decode(blockIdx.x, gridDim.x, blk, rhs);
+  if (wk.mask && wk.mask[rhs] == 0) return;   // uniform over the workgroup
+  const Field<S> out = out_b.at(rhs), in = in_b.at(rhs), w = w_b.at(rhs), dotf = dotf_b.at(rhs);
+  const SiteRef r = geo.locate(blk, sl, ns, Ls, s);
+  const bool valid = inb && r.valid;
 
   T h[24], y[24];
   if (valid) geo.template hop<DAG>(in, r, s, Ls, h);
@@ -484,7 +508,7 @@ k_hop(Geo geo, Field<S> out, Field<S> in, Field<S> w, Field<S> dotf, int Ls, int
       for (int k = 0; k < 24; ++k) loc += pv[k] * y[k];
     }
     const double tot = block_sum((double)loc, red);
-    if (tid == 0) dot_partial[blk] = tot;
+    if (tid == 0) dot_partial[(int64_t)rhs * wk.nblk + blk] = tot;
   }
   if (valid) store_site(out, r.out5, y);
 }

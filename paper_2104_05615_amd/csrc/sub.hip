@@ -5,7 +5,9 @@
 //
 // All kernels here map threads like the site kernels: a block owns ns sites
 // of C of one subdomain and all their Ls slices, so per-block partial sums are
-// grouped by subdomain as [d][bps].
+// grouped by subdomain as [d][bps].  Batched launches put the RHS in
+// blockIdx.y: fields at RHS offsets (Field::at), per-subdomain scalars at
+// r * nsub, partials at r * nsub * bps; RHS with mask[r] == 0 are skipped.
 #include <stdexcept>
 #include <string>
 
@@ -53,8 +55,15 @@ __device__ __forceinline__ uint32_t c_global(const SubTables& tc, const Lattice&
 template <typename O, typename I>
 __global__ void __launch_bounds__(256)
 k_sub_restrict(Field<O> r, Field<I> rs, Field<I> ps, Field<I> t0, const calc_t<I>* E, Lattice lat, SubTables tc,
-               int Ls, int ns, double* partial) {
+               int Ls, int ns, double* partial, const int* mask) {
   using T = calc_t<I>;
+  const int rhs = blockIdx.y;
+  if (mask && mask[rhs] == 0) return;
+  r = r.at(rhs);
+  rs = rs.at(rhs);
+  ps = ps.at(rhs);
+  t0 = t0.at(rhs);
+  partial += (int64_t)rhs * gridDim.x;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* red = reinterpret_cast<double*>(lds_raw);
   T* mats = reinterpret_cast<T*>(red + 16);
@@ -85,10 +94,18 @@ k_sub_restrict(Field<O> r, Field<I> rs, Field<I> ps, Field<I> t0, const calc_t<I
 
 template <typename I>
 __global__ void __launch_bounds__(256)
-k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* alpha, int first, SubTables tc, int Ls,
-             int ns, double* partial) {
+k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* alpha, int nsub, int first,
+             SubTables tc, int Ls, int ns, double* partial, const int* mask) {
   using T = calc_t<I>;
   __shared__ double red[16];
+  const int rhs = blockIdx.y;
+  if (mask && mask[rhs] == 0) return;
+  zs = zs.at(rhs);
+  ps = ps.at(rhs);
+  rs = rs.at(rhs);
+  qs = qs.at(rhs);
+  alpha += (int64_t)rhs * nsub;
+  partial += (int64_t)rhs * gridDim.x;
   const CSite c = c_site(tc, ns, Ls);
   double loc = 0;
   if (c.valid) {
@@ -119,9 +136,15 @@ k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* a
 
 template <typename I>
 __global__ void __launch_bounds__(256)
-k_sub_xpay5(Field<I> ps, Field<I> rs, Field<I> t0, const double* beta, const calc_t<I>* E, SubTables tc, int Ls,
-            int ns) {
+k_sub_xpay5(Field<I> ps, Field<I> rs, Field<I> t0, const double* beta, int nsub, const calc_t<I>* E, SubTables tc,
+            int Ls, int ns, const int* mask) {
   using T = calc_t<I>;
+  const int rhs = blockIdx.y;
+  if (mask && mask[rhs] == 0) return;
+  ps = ps.at(rhs);
+  rs = rs.at(rhs);
+  t0 = t0.at(rhs);
+  beta += (int64_t)rhs * nsub;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* red = reinterpret_cast<double*>(lds_raw);
   T* mats = reinterpret_cast<T*>(red + 16);
@@ -151,9 +174,17 @@ k_sub_xpay5(Field<I> ps, Field<I> rs, Field<I> t0, const double* beta, const cal
 template <typename O, typename I>
 __global__ void __launch_bounds__(256)
 k_sub_prolong(Field<O> z, Field<I> zs, Field<O> r, Field<O> rold, int has_rold, Lattice lat, SubTables tc, int Ls,
-              int ns, double* partial1, double* partial2) {
+              int ns, double* partial1, double* partial2, const int* mask) {
   using T = calc_t<O>;
   __shared__ double red[16];
+  const int rhs = blockIdx.y;
+  if (mask && mask[rhs] == 0) return;
+  z = z.at(rhs);
+  zs = zs.at(rhs);
+  r = r.at(rhs);
+  rold = rold.at(rhs);
+  partial1 += (int64_t)rhs * gridDim.x;
+  if (partial2) partial2 += (int64_t)rhs * gridDim.x;
   const CSite c = c_site(tc, ns, Ls);
   double l1 = 0, l2 = 0;
   if (c.valid) {
@@ -184,9 +215,17 @@ k_sub_prolong(Field<O> z, Field<I> zs, Field<O> r, Field<O> rold, int has_rold, 
 // then a fixed butterfly over the 64 lanes -- deterministic
 __global__ void __launch_bounds__(64)
 k_sub_finish(const double* partial, int bps, int nsub, double* rho, double* alpha, double* beta, int* active,
-             int mode) {
+             int mode, const int* mask) {
   const int d = blockIdx.x;
   const int lane = threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (mask && mask[rhs] == 0) return;
+  const int64_t so = (int64_t)rhs * nsub;
+  partial += so * bps;
+  rho += so;
+  alpha += so;
+  beta += so;
+  active += so;
   double S = 0;
   for (int b = lane; b < bps; b += 64) S += partial[(int64_t)d * bps + b];
   for (int off = 32; off > 0; off >>= 1) S += __shfl_xor(S, off);
@@ -213,115 +252,124 @@ k_sub_finish(const double* partial, int bps, int nsub, double* rho, double* alph
 
 static int c_ns(int Ls, Prec p) { return sites_per_block(Ls, p); }
 
+static dim3 c_grid(int nsub, const SubTables& tc, const Batch& bt) {
+  return dim3((unsigned)((int64_t)nsub * tc.bps), (unsigned)bt.n);
+}
+
 template <typename O, typename I>
 static void restrict_t(hipStream_t st, const FieldPtr& r, const FieldPtr& rs, const FieldPtr& ps, const FieldPtr& t0,
-                       const void* E, const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* partial) {
+                       const void* E, const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* partial,
+                       const Batch& bt) {
   using T = calc_t<I>;
   const int ns = c_ns(Ls, rs.prec);
   const size_t lds = 16 * sizeof(double) + sizeof(T) * (size_t)(2 * Ls * Ls + ns * tile_stride(Ls));
-  hipLaunchKernelGGL((k_sub_restrict<O, I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)),
-                     lds, st, typed<O>(r), typed<I>(rs), typed<I>(ps), typed<I>(t0), (const T*)E, lat, tc, Ls, ns,
-                     partial);
+  hipLaunchKernelGGL((k_sub_restrict<O, I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), lds, st,
+                     typed<O>(r), typed<I>(rs), typed<I>(ps), typed<I>(t0), (const T*)E, lat, tc, Ls, ns, partial,
+                     bt.mask);
   LAUNCH_CHECK();
 }
 
 template <typename O>
 static void restrict_o(hipStream_t st, Prec inner, const FieldPtr& r, const FieldPtr& rs, const FieldPtr& ps,
                        const FieldPtr& t0, const void* E, const Lattice& lat, const SubTables& tc, int nsub, int Ls,
-                       double* partial) {
+                       double* partial, const Batch& bt) {
   switch (inner) {
-    case Prec::F64: restrict_t<O, double>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
-    case Prec::F32: restrict_t<O, float>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
-    case Prec::F16: restrict_t<O, __half>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
-    case Prec::BF16: restrict_t<O, __hip_bfloat16>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial); break;
+    case Prec::F64: restrict_t<O, double>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
+    case Prec::F32: restrict_t<O, float>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
+    case Prec::F16: restrict_t<O, __half>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
+    case Prec::BF16: restrict_t<O, __hip_bfloat16>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
   }
 }
 
 void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_outer, const FieldPtr& rs,
                   const FieldPtr& ps, const FieldPtr& t0, const void* E, const Lattice& lat, const SubTables& tc,
-                  int nsub, int Ls, double* partial) {
-  if (outer == Prec::F64) restrict_o<double>(st, inner, r_outer, rs, ps, t0, E, lat, tc, nsub, Ls, partial);
-  else if (outer == Prec::F32) restrict_o<float>(st, inner, r_outer, rs, ps, t0, E, lat, tc, nsub, Ls, partial);
+                  int nsub, int Ls, double* partial, const Batch& bt) {
+  if (outer == Prec::F64) restrict_o<double>(st, inner, r_outer, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt);
+  else if (outer == Prec::F32) restrict_o<float>(st, inner, r_outer, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt);
   else throw std::runtime_error("sub_restrict: outer precision must be FP64 or FP32");
 }
 
 template <typename I>
 static void update_t(hipStream_t st, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& qs,
-                     const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls, double* partial) {
+                     const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls, double* partial,
+                     const Batch& bt) {
   const int ns = c_ns(Ls, zs.prec);
-  hipLaunchKernelGGL((k_sub_update<I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)), 0,
-                     st, typed<I>(zs), typed<I>(ps), typed<I>(rs), typed<I>(qs), sc.alpha, first ? 1 : 0, tc, Ls, ns,
-                     partial);
+  hipLaunchKernelGGL((k_sub_update<I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), 0, st, typed<I>(zs),
+                     typed<I>(ps), typed<I>(rs), typed<I>(qs), sc.alpha, nsub, first ? 1 : 0, tc, Ls, ns, partial,
+                     bt.mask);
   LAUNCH_CHECK();
 }
 
 void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
                 const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
-                double* partial) {
+                double* partial, const Batch& bt) {
   switch (inner) {
-    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
-    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
-    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
-    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial); break;
+    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
+    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
+    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
+    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
   }
 }
 
 template <typename I>
 static void xpay5_t(hipStream_t st, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0, const SubScalars& sc,
-                    const void* E, const SubTables& tc, int nsub, int Ls) {
+                    const void* E, const SubTables& tc, int nsub, int Ls, const Batch& bt) {
   using T = calc_t<I>;
   const int ns = c_ns(Ls, ps.prec);
   const size_t lds = 16 * sizeof(double) + sizeof(T) * (size_t)(2 * Ls * Ls + ns * tile_stride(Ls));
-  hipLaunchKernelGGL((k_sub_xpay5<I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)), lds,
-                     st, typed<I>(ps), typed<I>(rs), typed<I>(t0), sc.beta, (const T*)E, tc, Ls, ns);
+  hipLaunchKernelGGL((k_sub_xpay5<I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), lds, st, typed<I>(ps),
+                     typed<I>(rs), typed<I>(t0), sc.beta, nsub, (const T*)E, tc, Ls, ns, bt.mask);
   LAUNCH_CHECK();
 }
 
 void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0,
-               const SubScalars& sc, const void* E, const SubTables& tc, int nsub, int Ls) {
+               const SubScalars& sc, const void* E, const SubTables& tc, int nsub, int Ls, const Batch& bt) {
   switch (inner) {
-    case Prec::F64: xpay5_t<double>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
-    case Prec::F32: xpay5_t<float>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
-    case Prec::F16: xpay5_t<__half>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
-    case Prec::BF16: xpay5_t<__hip_bfloat16>(st, ps, rs, t0, sc, E, tc, nsub, Ls); break;
+    case Prec::F64: xpay5_t<double>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
+    case Prec::F32: xpay5_t<float>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
+    case Prec::F16: xpay5_t<__half>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
+    case Prec::BF16: xpay5_t<__hip_bfloat16>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
   }
 }
 
 template <typename O, typename I>
 static void prolong_t(hipStream_t st, const FieldPtr& z, const FieldPtr& zs, const FieldPtr& r, const FieldPtr* rold,
-                      const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* p1, double* p2) {
+                      const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* p1, double* p2,
+                      const Batch& bt) {
   const int ns = c_ns(Ls, zs.prec);
   Field<O> ro = rold ? typed<O>(*rold) : Field<O>{};
-  hipLaunchKernelGGL((k_sub_prolong<O, I>), dim3((unsigned)((int64_t)nsub * tc.bps)), dim3(site_block_threads(ns, Ls)),
-                     0, st, typed<O>(z), typed<I>(zs), typed<O>(r), ro, rold ? 1 : 0, lat, tc, Ls, ns, p1, p2);
+  hipLaunchKernelGGL((k_sub_prolong<O, I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), 0, st,
+                     typed<O>(z), typed<I>(zs), typed<O>(r), ro, rold ? 1 : 0, lat, tc, Ls, ns, p1,
+                     rold ? p2 : nullptr, bt.mask);
   LAUNCH_CHECK();
 }
 
 template <typename O>
 static void prolong_o(hipStream_t st, Prec inner, const FieldPtr& z, const FieldPtr& zs, const FieldPtr& r,
                       const FieldPtr* rold, const Lattice& lat, const SubTables& tc, int nsub, int Ls, double* p1,
-                      double* p2) {
+                      double* p2, const Batch& bt) {
   switch (inner) {
-    case Prec::F64: prolong_t<O, double>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
-    case Prec::F32: prolong_t<O, float>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
-    case Prec::F16: prolong_t<O, __half>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
-    case Prec::BF16: prolong_t<O, __hip_bfloat16>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2); break;
+    case Prec::F64: prolong_t<O, double>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
+    case Prec::F32: prolong_t<O, float>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
+    case Prec::F16: prolong_t<O, __half>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
+    case Prec::BF16: prolong_t<O, __hip_bfloat16>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
   }
 }
 
 void sub_prolong(hipStream_t st, Prec outer, Prec inner, const FieldPtr& z_outer, const FieldPtr& zs,
                  const FieldPtr& r_outer, const FieldPtr* rold_outer, const Lattice& lat, const SubTables& tc,
-                 int nsub, int Ls, double* partial1, double* partial2) {
+                 int nsub, int Ls, double* partial1, double* partial2, const Batch& bt) {
   if (outer == Prec::F64) prolong_o<double>(st, inner, z_outer, zs, r_outer, rold_outer, lat, tc, nsub, Ls, partial1,
-                                            partial2);
+                                            partial2, bt);
   else if (outer == Prec::F32) prolong_o<float>(st, inner, z_outer, zs, r_outer, rold_outer, lat, tc, nsub, Ls,
-                                                partial1, partial2);
+                                                partial1, partial2, bt);
   else throw std::runtime_error("sub_prolong: outer precision must be FP64 or FP32");
 }
 
-void sub_finish(hipStream_t st, const double* partial, int bps, int nsub, const SubScalars& sc, int mode) {
-  hipLaunchKernelGGL(k_sub_finish, dim3((unsigned)nsub), dim3(64), 0, st, partial, bps, nsub, sc.rho,
-                     sc.alpha, sc.beta, sc.active, mode);
+void sub_finish(hipStream_t st, const double* partial, int bps, int nsub, const SubScalars& sc, int mode,
+                const Batch& bt) {
+  hipLaunchKernelGGL(k_sub_finish, dim3((unsigned)nsub, (unsigned)bt.n), dim3(64), 0, st, partial, bps, nsub, sc.rho,
+                     sc.alpha, sc.beta, sc.active, mode, bt.mask);
   LAUNCH_CHECK();
 }
 

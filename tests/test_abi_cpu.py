@@ -96,3 +96,58 @@ def test_tiling_rule_matches_oracle():
                         assert got == want, sub
     finally:
         s.close()
+
+
+def test_batch_and_tuning_entry_points_validate_before_the_device():
+    import paper_2104_05615_amd as M
+    h = ctypes.c_void_p()
+    assert M.mspcg_create(ctypes.byref(h), (ctypes.c_int32 * 4)(8, 8, 8, 8), 0) == M.MSPCG_OK
+    try:
+        buf = (ctypes.c_double * 16)()
+        stats = (M.mspcg_stats * 2)()
+        assert M.mspcg_solve_batch_device(h, 0, buf, buf, None, None, stats) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_solve_batch_device(h, 2000, buf, buf, None, None, stats) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_solve_batch_device(h, 2, None, buf, None, None, stats) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_solve_batch_device(h, 2, buf, buf, None, None, stats) == M.MSPCG_ERR_NO_GAUGE
+        assert M.mspcg_autotune(h, 0) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_autotune(h, 2) == M.MSPCG_ERR_NO_GAUGE
+        o, x, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        assert M.mspcg_get_schedule(h, 5, 1, ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)) == \
+            M.MSPCG_ERR_INVALID_ARG
+        # untuned default: one RHS keeps the RHS-outer order, XCD ranges on
+        assert M.mspcg_get_schedule(h, 0, 1, ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)) == M.MSPCG_OK
+        assert (o.value, x.value, us.value) == (0, 1, 0.0)
+        assert M.mspcg_get_schedule(h, 2, 4, ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)) == M.MSPCG_OK
+        assert o.value == 1
+        e, a = ctypes.c_int64(), ctypes.c_int64()
+        assert M.mspcg_footprint(h, 1, ctypes.byref(e), ctypes.byref(a)) == M.MSPCG_ERR_NO_PARAMS
+        assert M.mspcg_share_gauge(h, h) == M.MSPCG_ERR_NO_GAUGE
+    finally:
+        M.mspcg_destroy(h)
+
+
+def test_server_lifecycle_and_validation_without_device_work():
+    import paper_2104_05615_amd as M
+    s = ctypes.c_void_p()
+    assert M.mspcg_server_create(ctypes.byref(s), 0, 0, 4) == M.MSPCG_ERR_INVALID_ARG
+    assert M.mspcg_server_create(ctypes.byref(s), 0, 1 << 30, 0) == M.MSPCG_ERR_INVALID_ARG
+    assert M.mspcg_server_create(ctypes.byref(s), 0, 1 << 30, 3) == M.MSPCG_OK
+    try:
+        info = M.mspcg_server_stats()
+        assert M.mspcg_server_info(s, ctypes.byref(info)) == M.MSPCG_OK
+        assert info.budget == 1 << 30 and info.bytes_in_use == 0 and info.inflight == 0
+        buf = (ctypes.c_double * 16)()
+        r = M.mspcg_request(0, 8, 1.5, 0.5, 1.8, 0.1, (ctypes.c_int32 * 4)(4, 4, 4, 4),
+                            M._solver_params(), 1, ctypes.cast(buf, ctypes.c_void_p),
+                            ctypes.cast(buf, ctypes.c_void_p))
+        t = ctypes.c_int64()
+        assert M.mspcg_server_submit(s, ctypes.byref(r), ctypes.byref(t)) == M.MSPCG_ERR_INVALID_ARG  # no field
+        assert "field" in M.mspcg_last_error().decode()
+        r.nrhs = 0
+        assert M.mspcg_server_submit(s, ctypes.byref(r), ctypes.byref(t)) == M.MSPCG_ERR_INVALID_ARG
+        d = ctypes.c_int32()
+        assert M.mspcg_server_poll(s, 12345, ctypes.byref(d)) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_server_wait(s, 12345, None, None) == M.MSPCG_ERR_INVALID_ARG
+    finally:
+        assert M.mspcg_server_destroy(s) == M.MSPCG_OK
+    assert M.mspcg_server_destroy(None) == M.MSPCG_OK

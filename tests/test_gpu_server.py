@@ -1,0 +1,158 @@
+"""GPU: the request loop (mspcg_server_*) -- resident fields and contexts,
+admission by device footprint, concurrent requests on separate streams.
+
+A request's arithmetic does not depend on what runs beside it, so every
+result must be the same alone (one request at a time) and in the mix (up
+to four requests in flight): same iteration counts and the same solution,
+bit for bit -- inside the stated tolerance by a wide margin.  The oracle
+checks the residuals.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MOB = (1.5, 0.5, 1.8)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_resid(op, b, x):
+    return float(np.linalg.norm(b - op.A(x)) / np.linalg.norm(b))
+
+
+FIELDS = {"A": ((8, 4, 4, 4), 0.5, 21), "B": ((8, 8, 4, 4), 0.4, 22)}
+
+# field, Ls, mf, sub, nrhs, solver
+REQUESTS = [
+    ("A", 4, 0.05, (4, 4, 4, 4), 2, dict(inner_iters=3)),
+    ("B", 6, 0.1, (4, 4, 4, 4), 1, dict(inner_iters=4)),
+    ("A", 4, 0.1, (4, 4, 4, 4), 3, dict(inner_iters=3, inner_prec="bf16")),
+    ("B", 6, 0.05, (4, 4, 4, 4), 2, dict(inner_iters=4)),
+    ("A", 5, 0.05, None, 1, dict(use_precond=False, beta_rule="FR")),
+    ("A", 4, 0.05, (4, 4, 4, 4), 2, dict(inner_iters=3)),     # same shape as the first: context reuse
+]
+
+
+def sources(i, dims, Ls, nrhs):
+    return [W.gaussian_source(dims, Ls, 700 + 10 * i + k) for k in range(nrhs)]
+
+
+def run(max_inflight, budget=64 << 30, order=None):
+    import torch
+    from paper_2104_05615_amd import Server
+    srv = Server(0, budget, max_inflight)
+    ids = {k: srv.add_field(d, W.gauge_field(d, eps, seed)) for k, (d, eps, seed) in FIELDS.items()}
+    bufs, out = [], {}
+    tickets = []
+    idx = order if order is not None else range(len(REQUESTS))
+    for i in idx:
+        f, Ls, mf, sub, nrhs, solver = REQUESTS[i]
+        dims = FIELDS[f][0]
+        bs = sources(i, dims, Ls, nrhs)
+        bt = torch.from_numpy(np.concatenate([b.view(np.float64).ravel() for b in bs])).cuda()
+        xt = torch.empty_like(bt)
+        torch.cuda.synchronize()
+        t = srv.submit(ids[f], Ls, *MOB, mf, sub, nrhs, bt.data_ptr(), xt.data_ptr(), tol=1e-10, maxiter=4000,
+                       **solver)
+        bufs.append((i, bt, xt, bs))
+        tickets.append((i, t))
+        if max_inflight == 1:   # alone: finish each before the next arrives
+            out[i] = srv.wait(t)
+    for i, t in tickets:
+        if i not in out:
+            out[i] = srv.wait(t)
+    info = srv.info()
+    res = {}
+    for i, bt, xt, bs in bufs:
+        st, stats, lat = out[i]
+        x = xt.cpu().numpy().view(np.complex128).reshape((len(bs),) + bs[0].shape)
+        res[i] = (st, stats, lat, x, bs)
+    srv.close()
+    return res, info
+
+
+def test_server_results_same_alone_and_in_the_mix():
+    say("[gpu] server: requests one at a time")
+    alone, info1 = run(1)
+    say(f"      {info1}")
+    assert info1["peak_inflight"] == 1
+    assert info1["contexts"] < len(REQUESTS)           # the repeated shape reused its context
+    say("[gpu] server: all requests at once, 4 in flight, reversed arrival")
+    mix, info4 = run(4, order=list(reversed(range(len(REQUESTS)))))
+    say(f"      {info4}")
+    assert info4["peak_inflight"] >= 2
+    for i in range(len(REQUESTS)):
+        st1, s1, lat1, x1, bs = alone[i]
+        st4, s4, lat4, x4, _ = mix[i]
+        say(f"      request {i}: status {st1}/{st4} iters {[a.outer_iters for a in s1]} "
+            f"latency alone {lat1:.1f} ms, mix {lat4:.1f} ms")
+        assert st1 == 0 and st4 == 0
+        assert [a.outer_iters for a in s1] == [a.outer_iters for a in s4]
+        assert np.array_equal(x1, x4)
+    # residuals of two of them against the oracle
+    for i in (1, 2):
+        f, Ls, mf, sub, nrhs, solver = REQUESTS[i]
+        d, eps, seed = FIELDS[f]
+        op = oracle.MobiusDWF(W.gauge_field(d, eps, seed), Ls, *MOB, mf)
+        _, _, _, x, bs = mix[i]
+        for k in range(nrhs):
+            assert oracle_resid(op, bs[k], x[k]) < 2e-10
+
+
+def test_server_admission_by_budget_and_oom():
+    from paper_2104_05615_amd import MSPCG, MSPCG_ERR_OOM
+    # footprint of the largest request shape, from a handle of the same shape
+    d, eps, seed = FIELDS["B"]
+    h = MSPCG(d)
+    h.load_gauge(W.gauge_field(d, eps, seed))
+    h.set_mobius(6, *MOB, 0.1)
+    h.set_subdomains((4, 4, 4, 4))
+    h.set_solver(tol=1e-10, inner_iters=4)
+    est, _ = h.footprint(2)
+    h.close()
+    fields = sum(int(np.prod(v[0])) * 4 * 9 * 24 for v in FIELDS.values())
+    budget = fields + int(1.3 * est)
+    say(f"[gpu] server: budget {budget} B = fields {fields} + 1.3 x {est}")
+    res, info = run(4, budget=budget)
+    say(f"      {info}")
+    assert info["bytes_peak"] <= budget
+    assert info["peak_inflight"] >= 1
+    for i, (st, stats, lat, x, bs) in res.items():
+        assert st == 0, (i, st)
+    # a budget below one request: the request fails with OOM, the server keeps running
+    say("[gpu] server: budget below one request")
+    res, info = run(2, budget=fields + est // 4)
+    assert all(v[0] == MSPCG_ERR_OOM for v in res.values())
+
+
+def test_footprint_estimate_covers_the_allocation():
+    import torch
+    from paper_2104_05615_amd import MSPCG
+    d, eps, seed = FIELDS["B"]
+    for solver, nrhs in ((dict(inner_iters=3), 3), (dict(use_precond=False, outer_prec="fp64"), 2),
+                         (dict(inner_iters=2, inner_prec="fp32"), 1)):
+        h = MSPCG(d)
+        h.load_gauge(W.gauge_field(d, eps, seed))
+        h.set_mobius(6, *MOB, 0.1)
+        h.set_subdomains((4, 4, 4, 4))
+        h.set_solver(tol=1e-8, maxiter=500, **solver)
+        est, _ = h.footprint(nrhs)
+        bs = [W.gaussian_source(d, 6, 800 + k) for k in range(nrhs)]
+        bt = torch.from_numpy(np.concatenate([b.view(np.float64).ravel() for b in bs])).cuda()
+        xt = torch.empty_like(bt)
+        say(f"[gpu] footprint {solver} nrhs={nrhs}")
+        st, stats = h.solve_batch_device(nrhs, bt.data_ptr(), xt.data_ptr())
+        _, alloc = h.footprint(nrhs)
+        say(f"      estimate {est} allocated {alloc}")
+        assert st == 0
+        assert alloc <= est and alloc >= 0.9 * est
+        h.close()
