@@ -84,6 +84,184 @@ STAGE_NAMES = {
 }
 
 
+# ---------------------------------------------------------------- serving stream
+
+# request volumes of the serving stream: name -> (dims, Ls, subdomain tiling)
+SERVE_VOLUMES = {
+    "8^4x8": ((8, 8, 8, 8), 8, (4, 4, 4, 4)),
+    "16^3x32x12": ((16, 16, 16, 32), 12, (4, 4, 4, 8)),
+    "24^3x48x16": ((24, 24, 24, 48), 16, (6, 6, 6, 12)),
+    "32^3x64x12": ((32, 32, 32, 64), 12, (8, 8, 8, 16)),
+}
+SERVE_FULL = dict(volumes=list(SERVE_VOLUMES), masses=[0.1, 0.01, 0.001], max_rhs=8)
+SERVE_SAMPLE = dict(volumes=["8^4x8", "16^3x32x12"], masses=[0.1, 0.01], max_rhs=3)
+
+
+def serve_stream(volumes, masses, max_rhs, nreq, seed=105, load=0.75, budget_gb=200, max_inflight=4,
+                 inner_iters=6):
+    """Poisson stream of batched solves through the library's request server.
+
+    Requests draw a volume, a mass and 1..max_rhs Gaussian sources (seeded,
+    generated on the device); the gauge fields (one per volume, links
+    exp(i 0.5 H), seeds 105, 106, ...) are resident.  The service time of each
+    (volume, mass) is measured once, alone, with one RHS; the arrival rate is
+    `load` times the capacity those times imply for serving the drawn
+    requests one after another.  Latency is submit -> completion, measured by
+    the server."""
+    import threading
+    import torch
+    import workloads as W
+    from paper_2104_05615_amd import Server
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(nreq):
+        reqs.append((volumes[int(rng.integers(len(volumes)))], float(masses[int(rng.integers(len(masses)))]),
+                     int(rng.integers(1, max_rhs + 1))))
+    gaps = rng.exponential(1.0, size=nreq)
+    srv = Server(0, int(budget_gb) << 30, max_inflight)
+    fid = {}
+    for k, name in enumerate(volumes):
+        dims, Ls, sub = SERVE_VOLUMES[name]
+        fid[name] = srv.add_field(dims, W.gauge_field(dims, 0.5, seed + k))
+    solver = dict(tol=1e-10, maxiter=100000, inner_iters=inner_iters, inner_prec="fp16", outer_prec="fp32")
+    stream = torch.cuda.current_stream()
+
+    def make(name, nrhs, s):
+        dims, Ls, sub = SERVE_VOLUMES[name]
+        n = nrhs * Ls * int(np.prod(dims)) // 2 * 24
+        g = torch.Generator(device="cuda")
+        g.manual_seed(s)
+        b = torch.randn(n, generator=g, device="cuda", dtype=torch.float64)
+        return b, torch.empty_like(b)
+
+    def submit(name, mf, nrhs, b, x):
+        dims, Ls, sub = SERVE_VOLUMES[name]
+        stream.synchronize()
+        return srv.submit(fid[name], Ls, 1.5, 0.5, 1.8, mf, sub, nrhs, b.data_ptr(), x.data_ptr(), **solver)
+
+    # service time per (volume, mass), one RHS, alone (also creates the contexts)
+    svc = {}
+    for name, mf in sorted({(r[0], r[1]) for r in reqs}):
+        b, x = make(name, 1, 1)
+        st, stats, lat = srv.wait(submit(name, mf, 1, b, x))
+        assert st == 0, (name, mf, st)
+        svc[(name, mf)] = lat / 1e3
+        log(f"[serve] alone {name} mf={mf}: {lat / 1e3:.3f}s, {stats[0].outer_iters} iters")
+    work = sum(svc[(n, m)] * k for n, m, k in reqs)
+    capacity = nreq / work
+    lam = load * capacity
+    log(f"[serve] {nreq} requests, sequential work {work:.1f}s, capacity {capacity:.3f}/s, "
+        f"arrival rate {lam:.3f}/s")
+    results = [None] * nreq
+    pending = []
+    cv = threading.Condition()
+    done_submitting = [False]
+
+    def waiter():
+        while True:
+            with cv:
+                while not pending and not done_submitting[0]:
+                    cv.wait()
+                if not pending:
+                    return
+                i, t, bufs = pending.pop(0)
+            results[i] = srv.wait(t)
+            del bufs
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    t_next = 0.0
+    for i, (name, mf, nrhs) in enumerate(reqs):
+        t_next += gaps[i] / lam
+        b, x = make(name, nrhs, 1000 + i)
+        delay = t0 + t_next - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        t = submit(name, mf, nrhs, b, x)
+        with cv:
+            pending.append((i, t, (b, x)))
+            cv.notify()
+    with cv:
+        done_submitting[0] = True
+        cv.notify()
+    th.join()
+    makespan = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    lats = np.array([r[2] for r in results]) / 1e3
+    ok = all(r[0] == 0 for r in results)
+    nrhs_tot = sum(r[2] for r in reqs)
+    out = {"requests": nreq, "rhs": nrhs_tot, "all_converged": ok,
+           "p50_s": float(np.percentile(lats, 50)), "p99_s": float(np.percentile(lats, 99)),
+           "mean_s": float(lats.mean()), "max_s": float(lats.max()),
+           "solves_per_s": nreq / makespan, "rhs_per_s": nrhs_tot / makespan, "makespan_s": makespan,
+           "arrival_rate_per_s": lam, "capacity_sequential_per_s": capacity, "load": load,
+           "max_inflight": max_inflight, "budget_bytes": info["budget"], "peak_bytes": info["bytes_peak"],
+           "peak_inflight": info["peak_inflight"], "contexts": info["contexts"], "evictions": info["evictions"],
+           "mix": {"volumes": volumes, "masses": masses, "rhs": [1, max_rhs], "seed": seed,
+                   "service_alone_s": {f"{n} mf={m}": v for (n, m), v in svc.items()}}}
+    log(f"[serve] p50 {out['p50_s']:.3f}s p99 {out['p99_s']:.3f}s, {out['solves_per_s']:.3f} solves/s, "
+        f"peak in flight {info['peak_inflight']}")
+    return out
+
+
+# ---------------------------------------------------------------- batched multi-RHS (16^4 x Ls16, 12 sources)
+
+def batch_bench(args):
+    import torch
+    import workloads as W
+    from workloads.configs import CONFIGS
+    from paper_2104_05615_amd import MSPCG, KIND_FP64, KIND_INNER, KIND_OUTER
+    cfg = CONFIGS["c3"]
+    log(f"[batch] workload {cfg.name}: {cfg.note}")
+    U = W.gauge_field(cfg.dims, cfg.eps, cfg.gauge_seed)
+    B = W.point_smeared_sources(cfg.dims, cfg.Ls, cfg.src_seed, cfg.nrhs)
+    s = MSPCG(cfg.dims)
+    s.load_gauge(U)
+    s.set_mobius(cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
+    s.set_subdomains(cfg.sub)
+    n = cfg.nrhs
+    bt = torch.from_numpy(B.view(np.float64).reshape(-1).copy()).cuda()
+    xt = torch.empty_like(bt)
+    per = bt.numel() // n
+    out = {"metric": "batched multi-RHS time-to-solution @ rel resid 1e-10", "unit": "s", "config": {
+        "workload": f"{cfg.name}: {cfg.note}", "lattice": list(cfg.dims), "Ls": cfg.Ls, "mf": cfg.mf,
+        "eps": cfg.eps, "subdomain": list(cfg.sub), "inner_iters": cfg.inner_iters, "nrhs": n,
+        "sources": "point-smeared (Gaussian profile, sigma 2, spin-colour unit vectors)"}}
+    for inner in ("fp16", "bf16"):
+        s.set_solver(tol=cfg.tol, maxiter=20000, inner_iters=cfg.inner_iters, inner_prec=inner, outer_prec="fp32")
+        # one RHS after another
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        seq = []
+        for r in range(n):
+            st = s.solve_device(bt[r * per:].data_ptr(), xt[r * per:].data_ptr())
+            seq.append(st)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t
+        log(f"[batch] {inner}: {n} single solves {t_seq:.2f}s, iters {[a.outer_iters for a in seq]}")
+        x_seq = xt.clone()
+        s.autotune(n)
+        sched = {k: s.schedule(kk, n) for k, kk in (("outer", KIND_OUTER), ("fp64", KIND_FP64),
+                                                  ("inner", KIND_INNER))}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, stats = s.solve_batch_device(n, bt.data_ptr(), xt.data_ptr())
+        torch.cuda.synchronize()
+        t_bat = time.perf_counter() - t
+        same = bool(torch.equal(x_seq, xt))
+        log(f"[batch] {inner}: batched {t_bat:.2f}s (status {st}), iters {[a.outer_iters for a in stats]}, "
+            f"identical to single solves: {same}")
+        out[inner] = {"sequential_s": t_seq, "batched_s": t_bat, "speedup": t_seq / t_bat, "status": st,
+                      "outer_iters": [a.outer_iters for a in stats],
+                      "true_rel_resid_max": max(a.true_rel_resid for a in stats),
+                      "identical_to_single_solves": same,
+                      "schedule": {k: {"order": v[0], "xcd": v[1], "four_hops_us": v[2]} for k, v in sched.items()}}
+    out["value"] = out["fp16"]["batched_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,10 +271,22 @@ def main():
     ap.add_argument("--inner-prec", default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve"])
+    ap.add_argument("--requests", type=int, default=None, help="serving stream length")
+    ap.add_argument("--serve-sample", type=int, default=12,
+                    help="requests of the serving sample in solve mode (0: none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus N > 1 is not supported"}))
         sys.exit(2)
+    if args.mode == "batch":
+        return batch_bench(args)
+    if args.mode == "serve":
+        import torch  # noqa: F401
+        r = serve_stream(nreq=args.requests or 200, **SERVE_FULL)
+        print(json.dumps({"metric": "serving p50/p99 latency and solves/s", "unit": "s", "value": r["p99_s"],
+                          "serve": r}), flush=True)
+        return
 
     import torch
     import workloads as W
@@ -222,6 +412,14 @@ def main():
         "roofline": roof,
         "p50_p99": None,
     }
+    if args.serve_sample > 0:
+        del s
+        r = serve_stream(nreq=args.serve_sample, **SERVE_SAMPLE)
+        line["p50_p99"] = {"p50_s": r["p50_s"], "p99_s": r["p99_s"], "solves_per_s": r["solves_per_s"],
+                           "sample": "serving sample: Poisson stream of %d requests over 8^4x8 and 16^3x32x12, "
+                                     "mf in {0.1, 0.01}, 1-3 RHS each, load %.2f of the measured sequential capacity"
+                                     % (r["requests"], r["load"]),
+                           "detail": r}
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, U, b, sts[-1].outer_iters, cg32[-1][1].outer_iters)

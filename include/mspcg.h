@@ -209,6 +209,21 @@ mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, d
  * none). */
 mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src);
 
+/* Engine of the fifth-dimension epilogue of the FP32 and 16-bit site kernels
+ * with Ls <= 16, for every handle of the process: 1 = MFMA (the default),
+ * 0 = vector ALUs.  Call it while no handle has work in flight; handles
+ * created before the call keep workspaces sized for the previous engine
+ * until set_mobius or set_subdomains.  Never fails. */
+mspcg_status mspcg_set_mfma(int32_t on);
+
+/* Graph replay of batched solves on (1, the default) or off (0: every
+ * iteration is launched eagerly; results are the same either way).  While
+ * a solve captures its graph (once per call, before the replays), device-wide
+ * synchronization from other threads of the process fails with a capture
+ * error; turn graphs off where other threads may synchronize the device.
+ * Errors: INVALID_ARG (NULL). */
+mspcg_status mspcg_set_graphs(mspcg_t h, int32_t on);
+
 /* Device memory of a handle: `estimate` = bytes a batched solve of nrhs
  * right-hand sides allocates with the current parameters (workspaces,
  * matrices, tables; not the gauge field), `allocated` = bytes the handle
@@ -275,6 +290,11 @@ mspcg_status mspcg_server_poll(mspcg_server_t s, int64_t ticket, int32_t* done);
  * the request's status (as mspcg_solve_batch_device; OOM when it cannot fit
  * the budget even alone; BAD_TILING or INVALID_ARG for bad parameters). */
 mspcg_status mspcg_server_wait(mspcg_server_t s, int64_t ticket, mspcg_stats* st, double* latency_ms);
+
+/* Graph replay on or off for every context of the server (as
+ * mspcg_set_graphs; off by default, since the caller's threads may
+ * synchronize the device at any time).  Errors: INVALID_ARG (NULL). */
+mspcg_status mspcg_server_set_graphs(mspcg_server_t s, int32_t on);
 
 /* Counters of the server. */
 mspcg_status mspcg_server_info(mspcg_server_t s, mspcg_server_stats* info);

@@ -97,6 +97,9 @@ _SIGS = {
     "mspcg_solve_batch_device": [_h, _i32, _p, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
     "mspcg_autotune": [_h, _i32],
     "mspcg_share_gauge": [_h, _h],
+    "mspcg_set_graphs": [_h, _i32],
+    "mspcg_set_mfma": [_i32],
+    "mspcg_server_set_graphs": [_h, _i32],
     "mspcg_footprint": [_h, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "mspcg_server_create": [ctypes.POINTER(_h), _i32, ctypes.c_int64, _i32],
     "mspcg_server_destroy": [_h],
@@ -209,6 +212,9 @@ class MSPCG:
                    reliable_delta=0.1, beta_rule="PR", use_precond=True):
         p = _solver_params(tol, maxiter, inner_iters, inner_prec, outer_prec, reliable_delta, beta_rule, use_precond)
         _check(mspcg_set_solver(self._h, ctypes.byref(p)))
+
+    def set_graphs(self, on=True):
+        _check(mspcg_set_graphs(self._h, 1 if on else 0))
 
     def share_gauge(self, other):
         _check(mspcg_share_gauge(self._h, other._h))
@@ -328,6 +334,9 @@ class Server:
         if st not in (MSPCG_OK, MSPCG_NOT_CONVERGED, MSPCG_ERR_BREAKDOWN, MSPCG_ERR_OOM):
             _check(st)
         return st, [_stats(a.status, a) for a in arr], lat.value
+
+    def set_graphs(self, on=True):
+        _check(mspcg_server_set_graphs(self._h, 1 if on else 0))
 
     def info(self):
         i = mspcg_server_stats()

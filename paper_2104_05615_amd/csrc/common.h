@@ -108,10 +108,13 @@ template <> __device__ __forceinline__ uint4 pack8<__hip_bfloat16>(const float* 
 }
 
 // Site access through raw buffer instructions: one 128-bit resource per
-// field (scalar registers), the site's byte offset in one vector register
-// shared by all chunks, and each chunk array's offset as a scalar.  A field
-// must be smaller than 4 GiB (checked on the host).  Accesses past the
-// resource's range read zero and drop stores.
+// field (scalar registers) and the byte offset of the site's chunk in a
+// vector register.  The scalar-offset operand is always 0: with the chunk
+// array's offset passed there, results of the subdomain kernels changed
+// from run to run on gfx950 when other kernels ran on the device at the same
+// time (vector offsets alone are reproducible).  A field must be smaller
+// than 4 GiB (checked on the host).  Accesses past the resource's range read
+// zero and drop stores.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -136,14 +139,14 @@ __device__ __forceinline__ void load_site(const Field<S>& f, uint32_t i, T* v) {
   if constexpr (sizeof(S) == 8) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * cs, 0, 0);
       v[2 * k] = __hiloint2double(c.y, c.x);
       v[2 * k + 1] = __hiloint2double(c.w, c.z);
     }
   } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * cs, 0, 0);
       v[4 * k] = __uint_as_float(c.x); v[4 * k + 1] = __uint_as_float(c.y);
       v[4 * k + 2] = __uint_as_float(c.z); v[4 * k + 3] = __uint_as_float(c.w);
     }
@@ -153,7 +156,7 @@ __device__ __forceinline__ void load_site(const Field<S>& f, uint32_t i, T* v) {
     float tmp[24];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * cs, 0, 0);
       uint4 q;
       q.x = c.x; q.y = c.y; q.z = c.z; q.w = c.w;
       unpack8<S>(q, tmp + 8 * k);
@@ -176,7 +179,7 @@ __device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const 
       const double a = (double)v[2 * k], b = (double)v[2 * k + 1];
       c.x = (uint32_t)__double2loint(a); c.y = (uint32_t)__double2hiint(a);
       c.z = (uint32_t)__double2loint(b); c.w = (uint32_t)__double2hiint(b);
-      __builtin_amdgcn_raw_buffer_store_b128(c, r, off, k * cs, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(c, r, off + k * cs, 0, 0);
     }
   } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
@@ -184,7 +187,7 @@ __device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const 
       u32x4 c;
       c.x = __float_as_uint((float)v[4 * k]); c.y = __float_as_uint((float)v[4 * k + 1]);
       c.z = __float_as_uint((float)v[4 * k + 2]); c.w = __float_as_uint((float)v[4 * k + 3]);
-      __builtin_amdgcn_raw_buffer_store_b128(c, r, off, k * cs, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(c, r, off + k * cs, 0, 0);
     }
   } else {
     float mx = 0.f;
@@ -199,7 +202,7 @@ __device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const 
       const uint4 q = pack8<S>(tmp + 8 * k);
       u32x4 c;
       c.x = q.x; c.y = q.y; c.z = q.z; c.w = q.w;
-      __builtin_amdgcn_raw_buffer_store_b128(c, r, off, k * cs, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(c, r, off + k * cs, 0, 0);
     }
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(mx), rs, i * 4u, 0, 0);
@@ -223,7 +226,7 @@ __device__ __forceinline__ T load_site_unscaled(const Field<S>& f, uint32_t i, T
     const float sc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * cs, 0, 0);
       uint4 q;
       q.x = c.x; q.y = c.y; q.z = c.z; q.w = c.w;
       unpack8<S>(q, v + 8 * k);
@@ -252,11 +255,11 @@ __device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu,
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     if constexpr (sizeof(C2) == 16) {
-      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, base + k * ks, 0);
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + base + k * ks, 0, 0);
       u[2 * k] = (T)__hiloint2double(c.y, c.x);
       u[2 * k + 1] = (T)__hiloint2double(c.w, c.z);
     } else {
-      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(r, off, base + k * ks, 0);
+      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(r, off + base + k * ks, 0, 0);
       u[2 * k] = (T)__uint_as_float(c.x);
       u[2 * k + 1] = (T)__uint_as_float(c.y);
     }
@@ -321,7 +324,7 @@ __device__ __forceinline__ float load_site_raw16(const Field<S>& f, uint32_t i, 
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off, k * cs, 0);
+    const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * cs, 0, 0);
     q[k].x = c.x; q[k].y = c.y; q[k].z = c.z; q[k].w = c.w;
   }
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));

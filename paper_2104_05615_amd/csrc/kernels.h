@@ -72,6 +72,9 @@ enum FinishMode { FIN_STORE = 0, FIN_ALPHA, FIN_RHO, FIN_BETA_FR, FIN_BETA_PR };
 // sites per block of the site kernels (16 when the MFMA epilogue is used)
 int sites_per_block(int Ls, Prec p);
 bool uses_mfma(int Ls, Prec p);
+// epilogue engine of every handle of the process (MFMA on by default)
+void set_mfma_epilogue(bool on);
+bool mfma_epilogue();
 int64_t full_blocks(int64_t vh, int Ls, Prec p);
 
 // ---------------------------------------------------------------- site kernels
@@ -111,7 +114,7 @@ void cg_update(hipStream_t st, Prec p, void* x, const void* pv, const void* r, c
 // partial Re<a,b1>, Re<a,b2> (b2 nullable)
 void dot2(hipStream_t st, Prec p, const void* a, const void* b1, const void* b2, int64_t nreal, double* partial1,
           double* partial2, int64_t nblocks, const Batch& bt = Batch());
-// r64 = b - Ax ; partial |r64|^2 ; r_lo = (float) r64 if r_lo
+// r64 = b - Ax (r64 nullable) ; partial |r64|^2 ; r_lo = (float) r64 if r_lo
 void residual64(hipStream_t st, const double* b, const double* Ax, double* r64, float* r_lo, int64_t n5,
                 double* partial, int64_t nblocks, const Batch& bt = Batch());
 // x64 += x_lo ; x_lo = 0

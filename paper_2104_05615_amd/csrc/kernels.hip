@@ -1,6 +1,7 @@
 // Full-lattice kernels: the hop operator with its fused epilogue, the
 // fifth-dimension-only operator, layout conversions, the outer solver's
 // BLAS-1 and deterministic reductions.
+#include <atomic>
 #include <stdexcept>
 #include <string>
 
@@ -16,7 +17,13 @@ namespace mspcg {
                                                    hipGetErrorString(e_));            \
   } while (0)
 
-bool uses_mfma(int Ls, Prec p) { return p != Prec::F64 && Ls <= 16; }
+// process-wide choice of the fifth-dimension epilogue engine for FP32 and
+// 16-bit site kernels with Ls <= 16: MFMA (default) or the vector ALUs
+static std::atomic<int> g_mfma_epilogue{1};
+void set_mfma_epilogue(bool on) { g_mfma_epilogue.store(on ? 1 : 0); }
+bool mfma_epilogue() { return g_mfma_epilogue.load() != 0; }
+
+bool uses_mfma(int Ls, Prec p) { return p != Prec::F64 && Ls <= 16 && mfma_epilogue(); }
 
 int sites_per_block(int Ls, Prec p) {
   if (uses_mfma(Ls, p)) return 16;
@@ -463,7 +470,7 @@ k_dot2(const C* a, const C* b1, const C* b2, int64_t n, double* partial1, double
 // numbers 2j and 2j+1 of that site; in FP64 they are chunks 2j and 2j+1.
 // Both layouts use stride n5 (chunks per chunk-array).
 
-// reliable update residual: r64 = b - Ax ; partial |r64|^2 ; r_lo = (float) r64 when given
+// reliable update residual: r64 = b - Ax (when given) ; partial |r64|^2 ; r_lo = (float) r64 when given
 __global__ void __launch_bounds__(256)
 k_residual64(const double2* b, const double2* Ax, double2* r64, float4* r_lo, int64_t n5, double* partial,
              const int* mask) {
@@ -472,7 +479,7 @@ k_residual64(const double2* b, const double2* Ax, double2* r64, float4* r_lo, in
   if (mask && mask[rhs] == 0) return;
   b += (int64_t)rhs * 12 * n5;
   Ax += (int64_t)rhs * 12 * n5;
-  r64 += (int64_t)rhs * 12 * n5;
+  if (r64) r64 += (int64_t)rhs * 12 * n5;
   if (r_lo) r_lo += (int64_t)rhs * 6 * n5;
   double loc = 0;
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < 6 * n5; f += (int64_t)gridDim.x * blockDim.x) {
@@ -480,8 +487,10 @@ k_residual64(const double2* b, const double2* Ax, double2* r64, float4* r_lo, in
     const int64_t ia = 2 * j * n5 + i, ib = ia + n5;
     const double2 b0 = b[ia], b1 = b[ib], a0 = Ax[ia], a1 = Ax[ib];
     const double2 o0 = make_double2(b0.x - a0.x, b0.y - a0.y), o1 = make_double2(b1.x - a1.x, b1.y - a1.y);
-    r64[ia] = o0;
-    r64[ib] = o1;
+    if (r64) {
+      r64[ia] = o0;
+      r64[ib] = o1;
+    }
     loc += o0.x * o0.x + o0.y * o0.y + o1.x * o1.x + o1.y * o1.y;
     if (r_lo) r_lo[f] = make_float4((float)o0.x, (float)o0.y, (float)o1.x, (float)o1.y);
   }

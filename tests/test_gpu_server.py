@@ -128,10 +128,12 @@ def test_server_admission_by_budget_and_oom():
     assert info["peak_inflight"] >= 1
     for i, (st, stats, lat, x, bs) in res.items():
         assert st == 0, (i, st)
-    # a budget below one request: the request fails with OOM, the server keeps running
+    # a budget below any request (every solve needs more than 1 MB of
+    # workspace here): each request fails with OOM, the server keeps running
     say("[gpu] server: budget below one request")
-    res, info = run(2, budget=fields + est // 4)
+    res, info = run(2, budget=fields + (256 << 10))
     assert all(v[0] == MSPCG_ERR_OOM for v in res.values())
+    assert info["completed"] == len(REQUESTS) and info["inflight"] == 0
 
 
 def test_footprint_estimate_covers_the_allocation():
