@@ -53,9 +53,12 @@ def stage_bytes(cfg, inner_prec):
     """Algorithmic bytes of one launch of each hop stage: every input site
     read once, every output written once, the epilogue's second field (w) and,
     in the last hop, the field of the fused <p, A p> partial read once where
-    they are nonzero, and the 8 FP32 links of each output 4D site read once
-    (shared over Ls).  Keys: profiling kinds of the library (21..24 outer FP32
-    hops of A, 11..14 subdomain hops h1..h4)."""
+    they are nonzero, and the FP32 links the launch needs read once each: the
+    8 links of each output 4D site (shared over Ls), at most every link of the
+    lattice (subdomain regions overlap their neighbours, so the links of one
+    launch of a subdomain hop repeat across subdomains).  Keys: profiling
+    kinds of the library (21..24 outer FP32 hops of A, 11..14 subdomain hops
+    h1..h4)."""
     X, Y, Z, T = cfg.dims
     vh = X * Y * Z * T // 2
     Ls = cfg.Ls
@@ -67,8 +70,9 @@ def stage_bytes(cfg, inner_prec):
            23: 2 * sp32 * n5 + link * vh, 24: 4 * sp32 * n5 + link * vh}
     nC, nN1, nN2 = region_counts(cfg.sub, cfg.dims)
     ns = cfg.n_subdomains
+    all_links = 2 * vh * 4 * 18 * 4
     for k, (sin, sout) in {11: (nC, nN1), 12: (nN1 + nC, nN2), 13: (nN2, nN1), 14: (nN1 + 2 * nC, nC)}.items():
-        out[k] = ns * (Ls * sp16 * (sin + sout) + link * sout)
+        out[k] = ns * Ls * sp16 * (sin + sout) + min(ns * link * sout, all_links)
     return out, (nC, nN1, nN2)
 
 
@@ -262,6 +266,77 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------- kernels only (for counter runs)
+
+def kernels_bench(args):
+    """A few applications of the outer operator A (FP32) and of the local
+    operator A_s (inner precision) on one workload, and a plain device copy
+    of 1 GiB whose counters calibrate the HBM byte counters.  No solve: a
+    short program for rocprofv3 counter passes."""
+    import torch
+    import workloads as W
+    from workloads.configs import CONFIGS
+    from paper_2104_05615_amd import MSPCG
+    cfg = CONFIGS[args.config]
+    inner = args.inner_prec or cfg.inner_prec
+    U = W.gauge_field(cfg.dims, cfg.eps, cfg.gauge_seed)
+    b = W.gaussian_source(cfg.dims, cfg.Ls, cfg.src_seed)
+    s = MSPCG(cfg.dims)
+    s.load_gauge(U)
+    s.set_mobius(cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
+    s.set_subdomains(cfg.sub)
+    s.set_solver(tol=cfg.tol, inner_iters=cfg.inner_iters, inner_prec=inner, outer_prec="fp32")
+    bt = torch.from_numpy(b.view(np.float64).reshape(-1).copy()).cuda()
+    xt = torch.empty_like(bt)
+    src = torch.ones(1 << 28, device="cuda", dtype=torch.float32)   # 1 GiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    out = {"mode": "kernels", "config": cfg.name, "copy_bytes": 2 * src.numel() * 4}
+    t = time.perf_counter()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_ms"] = 1e3 * (time.perf_counter() - t)
+    for op, prec in (("A", "fp32"), ("A_sub", inner)):
+        s.set_profiling(True)
+        for _ in range(args.steps):
+            s.apply_device(op, prec, bt.data_ptr(), xt.data_ptr())
+        torch.cuda.synchronize()
+        n_o, ms_o = s.kernel_time(0)
+        n_i, ms_i = s.kernel_time(1)
+        s.set_profiling(False)
+        out[f"{op}_{prec}"] = {"outer_hops": n_o, "outer_ms": ms_o, "inner_hops": n_i, "inner_ms": ms_i}
+        log(f"[kernels] {op} {prec}: {args.steps} applications")
+    print(json.dumps(out), flush=True)
+
+
+KERNEL_SOURCES = ["common.h", "sitekern.h", "kernels.h", "kernels.hip", "sub.hip"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_kernels_c2_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_05615_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch of a hop stage from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain
+    copy); None when the kernels changed since, or for another workload."""
+    try:
+        txt = open(TRAFFIC_SUMMARY).read()
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != kernel_source_hash() or blob.get("workload") != workload:
+        return None
+    k = blob.get("stages", {}).get(str(stage))
+    return None if k is None else k["traffic_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,7 +346,11 @@ def main():
     ap.add_argument("--inner-prec", default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve", "kernels"])
+    ap.add_argument("--log-every", type=int, default=0, help="solver progress line every N outer iterations")
+    ap.add_argument("--no-cg64", action="store_true", help="skip the FP64 CG baseline")
+    ap.add_argument("--oracle-check", action="store_true",
+                    help="relative residual of the MSPCG solution by the FP64 oracle on the host")
     ap.add_argument("--requests", type=int, default=None, help="serving stream length")
     ap.add_argument("--serve-sample", type=int, default=12,
                     help="requests of the serving sample in solve mode (0: none)")
@@ -281,6 +360,8 @@ def main():
         sys.exit(2)
     if args.mode == "batch":
         return batch_bench(args)
+    if args.mode == "kernels":
+        return kernels_bench(args)
     if args.mode == "serve":
         import torch  # noqa: F401
         r = serve_stream(nreq=args.requests or 200, **SERVE_FULL)
@@ -305,6 +386,7 @@ def main():
     s.load_gauge(U)
     s.set_mobius(cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
     s.set_subdomains(cfg.sub)
+    s.set_log(args.log_every)
     dev = torch.device("cuda:0")
     bt = torch.from_numpy(b.view(np.float64).reshape(-1).copy()).to(dev)
     xt = torch.empty_like(bt)
@@ -352,10 +434,13 @@ def main():
                beta_rule="FR", use_precond=False)
     log(f"[bench] CG fp32: {cg32[-1][0]:.3f}s, {cg32[-1][1].outer_iters} iters, "
         f"true resid {cg32[-1][1].true_rel_resid:.2e}")
-    cg64 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp64", reliable_delta=0.1,
-               beta_rule="FR", use_precond=False)
-    log(f"[bench] CG fp64: {cg64[-1][0]:.3f}s, {cg64[-1][1].outer_iters} iters, "
-        f"true resid {cg64[-1][1].true_rel_resid:.2e}")
+    if args.no_cg64:
+        cg64 = cg32
+    else:
+        cg64 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp64", reliable_delta=0.1,
+                   beta_rule="FR", use_precond=False)
+        log(f"[bench] CG fp64: {cg64[-1][0]:.3f}s, {cg64[-1][1].outer_iters} iters, "
+            f"true resid {cg64[-1][1].true_rel_resid:.2e}")
     x_cg = xt.clone()
     sol_rel = float(torch.linalg.vector_norm(x_ms - x_cg) / torch.linalg.vector_norm(x_cg))
 
@@ -367,10 +452,11 @@ def main():
             avg = ms / n
             kernels[str(k)] = {"name": STAGE_NAMES[k], "launches": n, "total_ms": ms, "avg_ms": avg,
                                "algorithmic_bytes": sbytes[k], "GBps": sbytes[k] / (avg * 1e-3) / 1e9}
-    dom = max(kernels.values(), key=lambda v: v["total_ms"])
+    dom_key, dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
     roof = {"kernel": dom["name"], "bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": dom["avg_ms"],
-            "launches": dom["launches"], "algorithmic_bytes_per_launch": dom["algorithmic_bytes"]}
+            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, dom_key),
+            "avg_launch_ms": dom["avg_ms"], "launches": dom["launches"],
+            "algorithmic_bytes_per_launch": dom["algorithmic_bytes"]}
     outer_b = sum(sbytes[k] for k in (21, 22, 23, 24)) / 4
     inner_b = sum(sbytes[k] for k in (11, 12, 13, 14)) / 4
     avg_out = ms_out / max(n_out, 1)
@@ -401,10 +487,10 @@ def main():
                   "precond_ms_per_solve": ms_pc / args.steps},
         "cg_fp32": {"time_s": cg32[-1][0], "outer_iters": cg32[-1][1].outer_iters,
                     "true_rel_resid": cg32[-1][1].true_rel_resid},
-        "cg_fp64": {"time_s": cg64[-1][0], "outer_iters": cg64[-1][1].outer_iters,
-                    "true_rel_resid": cg64[-1][1].true_rel_resid},
+        "cg_fp64": None if args.no_cg64 else {"time_s": cg64[-1][0], "outer_iters": cg64[-1][1].outer_iters,
+                                              "true_rel_resid": cg64[-1][1].true_rel_resid},
         "speedup_vs_cg_fp32": cg32[-1][0] / statistics.median(times),
-        "solution_rel_diff_mspcg_vs_cg64": sol_rel,
+        ("solution_rel_diff_mspcg_vs_cg32" if args.no_cg64 else "solution_rel_diff_mspcg_vs_cg64"): sol_rel,
         "kernels": kernels,
         "dslash": {"outer_hop_GBps": gbs_out, "outer_hop_avg_ms": avg_out, "outer_launches": n_out,
                    "inner_hop_GBps": gbs_in, "inner_hop_avg_ms": avg_in, "inner_launches": n_in,
@@ -412,6 +498,17 @@ def main():
         "roofline": roof,
         "p50_p99": None,
     }
+    if args.oracle_check:
+        os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+        import oracle
+        x = x_ms.cpu().numpy().view(np.complex128).reshape(b.shape)
+        log("[bench] oracle residual of the MSPCG solution: applying A on the host")
+        t = time.perf_counter()
+        op = oracle.MobiusDWF(U, cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
+        r = b - op.A(x)
+        res = float(np.linalg.norm(r) / np.linalg.norm(b))
+        log(f"[bench] oracle residual {res:.3e} ({time.perf_counter() - t:.1f}s)")
+        line["mspcg"]["oracle_rel_resid"] = res
     if args.serve_sample > 0:
         del s
         r = serve_stream(nreq=args.serve_sample, **SERVE_SAMPLE)

@@ -216,6 +216,11 @@ mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src);
  * until set_mobius or set_subdomains.  Never fails. */
 mspcg_status mspcg_set_mfma(int32_t on);
 
+/* Progress of long solves: one line on stderr every `every` outer
+ * iterations (the iterated relative residual; for batched solves the RHS
+ * still active), 0 = none (the default).  Errors: INVALID_ARG. */
+mspcg_status mspcg_set_log(mspcg_t h, int32_t every);
+
 /* Graph replay of batched solves on (1, the default) or off (0: every
  * iteration is launched eagerly; results are the same either way).  While
  * a solve captures its graph (once per call, before the replays), device-wide

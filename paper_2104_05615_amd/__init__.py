@@ -98,6 +98,7 @@ _SIGS = {
     "mspcg_autotune": [_h, _i32],
     "mspcg_share_gauge": [_h, _h],
     "mspcg_set_graphs": [_h, _i32],
+    "mspcg_set_log": [_h, _i32],
     "mspcg_set_mfma": [_i32],
     "mspcg_server_set_graphs": [_h, _i32],
     "mspcg_footprint": [_h, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
@@ -215,6 +216,9 @@ class MSPCG:
 
     def set_graphs(self, on=True):
         _check(mspcg_set_graphs(self._h, 1 if on else 0))
+
+    def set_log(self, every=0):
+        _check(mspcg_set_log(self._h, int(every)))
 
     def share_gauge(self, other):
         _check(mspcg_share_gauge(self._h, other._h))

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -321,6 +322,7 @@ struct mspcg_ctx {
 
   bool profiling = false;
   bool graphs = true;              // batched solves replay captured graphs
+  int log_every = 0;               // progress line to stderr every this many outer iterations (0: none)
   int64_t capture_fallbacks = 0;   // batched solves whose graph capture failed (ran eagerly)
   std::vector<EventPair> ev_pool;
   size_t ev_used = 0;
@@ -755,6 +757,9 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
       const double rn = std::sqrt(rr);
       S.iter_rel_resid = rn / bnorm;
       rmax = std::max(rmax, rn);
+      if (h->log_every > 0 && it % h->log_every == 0)
+        std::fprintf(stderr, "[mspcg] iteration %d  |r|/|b| = %.3e  reliable updates %d\n", it, rn / bnorm,
+                     S.reliable_updates);
       const bool conv = rn <= sp.tol * bnorm;
       const bool last = it >= sp.maxiter;
       const bool ru = conv || last || (delta > 0 && rn < delta * rmax);
@@ -1017,6 +1022,9 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
         if (k > 0) {
           HIPCHK(hipEventSynchronize(fev[(k - 1) & 1]));
           if (h->h_flag[(k - 1) & 1] == 0) break;
+          if (h->log_every > 0 && (launched - 2) % h->log_every < 2)
+            std::fprintf(stderr, "[mspcg] batch: %lld iterations launched, %d of %d RHS active\n",
+                         (long long)(launched - 2), h->h_flag[(k - 1) & 1], n);
         }
         if (launched > limit) {
           HIPCHK(hipEventSynchronize(fev[k & 1]));
@@ -1478,6 +1486,15 @@ mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src) {
 mspcg_status mspcg_set_mfma(int32_t on) {
   return guarded([&]() -> mspcg_status {
     set_mfma_epilogue(on != 0);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_log(mspcg_t h, int32_t every) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (every < 0) throw Error(MSPCG_ERR_INVALID_ARG, "every must be >= 0");
+    h->log_every = every;
     return MSPCG_OK;
   });
 }
