@@ -140,6 +140,21 @@ mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0
 mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const double* x0, void* hip_stream,
                                 mspcg_stats* st);
 
+/* Solve the full five-dimensional system M psi = phi on both parities,
+ * M = [[M5, M4_eo], [M4_oe, M5]] with M4 = D^w M_phi (Sec. 2.2), through the
+ * even-odd Schur complement (eq. dirac_equation): phi^_e = M5^-1 phi_e -
+ * M5^-1 M4_eo M5^-1 phi_o; D^dag D psi_e = D^dag phi^_e by the configured
+ * solver (as mspcg_solve_device); psi_o = M5^-1 (phi_o - M4_oe psi_e).  The
+ * steps outside the solve run in FP64.
+ *   phi, psi: device FP64, the even field then the odd field, each of the
+ *             layout above (odd sites ordered by lex/2 like even ones).
+ *   st: nullable, stats of the even solve; full_rel_resid: nullable, gets
+ *   || phi - M psi || / || phi || computed in FP64.
+ * Runs on hip_stream (NULL = the handle's stream); returns when done.
+ * Returns as mspcg_solve_device. */
+mspcg_status mspcg_solve_full_device(mspcg_t h, const double* phi, double* psi, void* hip_stream, mspcg_stats* st,
+                                     double* full_rel_resid);
+
 /* Solve A x_r = b_r for nrhs right-hand sides on the loaded gauge field, each
  * by the same PCG as mspcg_solve_device (Alg. 1 with the reliable updates and
  * Polak-Ribiere beta of Sec. 3.2, preconditioner of Sec. 2.4-2.5).  Every

@@ -95,6 +95,7 @@ _SIGS = {
     "mspcg_solve": [_h, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
     "mspcg_solve_device": [_h, _p, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
     "mspcg_solve_batch_device": [_h, _i32, _p, _p, _p, _p, ctypes.POINTER(mspcg_stats)],
+    "mspcg_solve_full_device": [_h, _p, _p, _p, ctypes.POINTER(mspcg_stats), ctypes.POINTER(_d)],
     "mspcg_autotune": [_h, _i32],
     "mspcg_share_gauge": [_h, _h],
     "mspcg_set_graphs": [_h, _i32],
@@ -247,6 +248,27 @@ class MSPCG:
         st = _check(mspcg_solve_device(self._h, b_ptr, x_ptr, x0_ptr, stream, ctypes.byref(s)),
                     allow_not_converged=True)
         return _stats(st, s)
+
+    def solve_full_device(self, phi_ptr, psi_ptr, stream=None):
+        """Full 5D system on both parities (device FP64, even half then odd
+        half); returns (Stats of the even solve, ||phi - M psi|| / ||phi||)."""
+        s = mspcg_stats()
+        r = _d()
+        st = _check(mspcg_solve_full_device(self._h, phi_ptr, psi_ptr, stream, ctypes.byref(s), ctypes.byref(r)),
+                    allow_not_converged=True)
+        return _stats(st, s), r.value
+
+    def solve_full(self, phi_e, phi_o):
+        """Host convenience around solve_full_device: returns psi_e, psi_o, stats, full residual."""
+        import torch
+        n = self._n()
+        buf = np.concatenate([_host_f64(phi_e, n), _host_f64(phi_o, n)])
+        dphi = torch.from_numpy(buf).cuda()
+        dpsi = torch.empty_like(dphi)
+        torch.cuda.synchronize()
+        st, res = self.solve_full_device(dphi.data_ptr(), dpsi.data_ptr())
+        out = dpsi.cpu().numpy().view(np.complex128).reshape(2, self.Ls, self.vh, 4, 3)
+        return out[0], out[1], st, res
 
     def solve_batch_device(self, nrhs, b_ptr, x_ptr, x0_ptr=None, stream=None):
         """nrhs device FP64 fields one after another; returns (status, [Stats per RHS])."""

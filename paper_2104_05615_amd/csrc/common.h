@@ -236,8 +236,9 @@ __device__ __forceinline__ T load_site_unscaled(const Field<S>& f, uint32_t i, T
 }
 
 // --------------------------------------------------------------------------
-// gauge links: per parity, per direction, 9 complex entries (row-major) as
-// separate arrays of length vh:  U[parity][mu][entry][vh] of complex L2.
+// gauge links: per parity, per direction, per site one record of the 9
+// complex entries (row-major) padded to 10, so that a link is read with
+// 16-byte loads:  U[parity][mu][vh][10] of complex L2.
 // --------------------------------------------------------------------------
 template <typename L> struct Gauge {
   using c2 = typename std::conditional<sizeof(L) == 8, double2, float2>::type;
@@ -248,20 +249,25 @@ template <typename L> struct Gauge {
 template <typename L, typename T>
 __device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu, uint32_t site, T* u) {
   using C2 = typename Gauge<L>::c2;
-  const __amdgpu_buffer_rsrc_t r = make_rsrc(g.data, (uint64_t)72 * (uint64_t)g.vh * sizeof(C2));
-  const uint32_t ks = (uint32_t)g.vh * (uint32_t)sizeof(C2);
-  const uint32_t base = (uint32_t)((parity * 4 + mu) * 9) * ks;
-  const uint32_t off = site * (uint32_t)sizeof(C2);
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(g.data, (uint64_t)80 * (uint64_t)g.vh * sizeof(C2));
+  const uint32_t off = ((uint32_t)(parity * 4 + mu) * (uint32_t)g.vh + site) * 10u * (uint32_t)sizeof(C2);
+  if constexpr (sizeof(C2) == 16) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    if constexpr (sizeof(C2) == 16) {
-      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + base + k * ks, 0, 0);
+    for (int k = 0; k < 9; ++k) {
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * 16, 0, 0);
       u[2 * k] = (T)__hiloint2double(c.y, c.x);
       u[2 * k + 1] = (T)__hiloint2double(c.w, c.z);
-    } else {
-      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(r, off + base + k * ks, 0, 0);
-      u[2 * k] = (T)__uint_as_float(c.x);
-      u[2 * k + 1] = (T)__uint_as_float(c.y);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + j * 16, 0, 0);
+      u[4 * j] = (T)__uint_as_float(c.x);
+      u[4 * j + 1] = (T)__uint_as_float(c.y);
+      if (j < 4) {
+        u[4 * j + 2] = (T)__uint_as_float(c.z);
+        u[4 * j + 3] = (T)__uint_as_float(c.w);
+      }
     }
   }
 }

@@ -364,7 +364,7 @@ __global__ void k_pack_gauge(C2* out, const double* canon, Lattice lat) {
       C2 c;
       c.x = src[0];
       c.y = src[1];
-      out[((int64_t)(par * 4 + mu) * 9 + k) * lat.vh + cb] = c;
+      out[((int64_t)(par * 4 + mu) * lat.vh + cb) * 10 + k] = c;
     }
 }
 

@@ -820,6 +820,67 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
 }
 
 // --------------------------------------------------------------------------
+// The full 5D system M psi = phi on both parities (the block form of Sec.
+// 2.2, [[M5, M4_eo], [M4_oe, M5]] with M4 = D^w M_phi) through the even-odd
+// Schur complement (eq. dirac_equation):
+//   phi^_e = M5^-1 phi_e - M5^-1 M4_eo M5^-1 phi_o
+//   D^dag D psi_e = D^dag phi^_e        (the configured solver)
+//   psi_o = M5^-1 (phi_o - M4_oe psi_e)
+// Every step outside the solve is FP64; M4_eo M5^-1 phi_o is one hop of
+// Q phi_o (Q = M_phi M5^-1) with the M5^-1 epilogues fused.  full_resid
+// (nullable) gets || phi - M psi || / || phi || in FP64.
+// --------------------------------------------------------------------------
+mspcg_status solve_full_impl(mspcg_ctx* h, const double* phi, double* psi, hipStream_t st, mspcg_stats* stats,
+                             double* full_resid) {
+  const int64_t vh = h->lat.vh, n5 = h->n5(), half = n5 * 24;
+  const int Ls = h->Ls;
+  const Prec P = Prec::F64;
+  FieldPtr pe = h->field("f.pe", P, vh), po = h->field("f.po", P, vh), t = h->field("f.t", P, vh);
+  FieldPtr he = h->field("f.he", P, vh), bq = h->field("f.b", P, vh);
+  FieldPtr xe = h->field("f.xe", P, vh), xo = h->field("f.xo", P, vh);
+  double* bcan = h->buf("f.bcan", (size_t)half * sizeof(double)).as<double>();
+  pack_field(st, pe, phi, vh, Ls);
+  pack_field(st, po, phi + half, vh, Ls);
+  // phi^_e = M5^-1 phi_e - M5^-1 D^w_eo (Q phi_o) ; b = D^dag phi^_e
+  apply5_full(st, P, t, po, h->mat(P, MAT_Q), vh, Ls, nullptr);
+  h->hop(st, P, he, t, &pe, 0, false, h->epi(P, MAT_M5INV, MAT_NEG_M5INV));
+  h->Ddag_op(st, P, bq, he, "f");
+  unpack_field(st, bcan, bq, vh, Ls);
+  const mspcg_status status = solve_impl(h, bcan, psi, nullptr, st, stats);
+  if (status != MSPCG_OK && status != MSPCG_NOT_CONVERGED) return status;
+  // psi_o = M5^-1 phi_o - M5^-1 D^w_oe (M_phi psi_e)
+  pack_field(st, xe, psi, vh, Ls);
+  apply5_full(st, P, t, xe, h->mat(P, MAT_MPHI), vh, Ls, nullptr);
+  h->hop(st, P, xo, t, &po, 1, false, h->epi(P, MAT_M5INV, MAT_NEG_M5INV));
+  unpack_field(st, psi + half, xo, vh, Ls);
+  if (full_resid) {
+    // (M psi)_e = M5 psi_e + D^w_eo M_phi psi_o ; (M psi)_o = M5 psi_o + D^w_oe M_phi psi_e
+    FieldPtr me = h->field("f.me", P, vh), mo = h->field("f.mo", P, vh);
+    apply5_full(st, P, t, xo, h->mat(P, MAT_MPHI), vh, Ls, nullptr);
+    h->hop(st, P, me, t, &xe, 0, false, h->epi(P, MAT_M5, -1));
+    apply5_full(st, P, t, xe, h->mat(P, MAT_MPHI), vh, Ls, nullptr);
+    h->hop(st, P, mo, t, &xo, 1, false, h->epi(P, MAT_M5, -1));
+    const int64_t nbl64 = blas_blocks(half / 2);
+    double* part = h->partial("f.r", nbl64);
+    double* scal = h->scal();
+    double v[4];
+    const FieldPtr* a[4] = {&pe, &po, &pe, &po};
+    const FieldPtr* m[4] = {&me, &mo, nullptr, nullptr};
+    for (int k = 0; k < 4; ++k) {
+      if (m[k]) residual64(st, (const double*)a[k]->data, (const double*)m[k]->data, nullptr, nullptr, n5, part, nbl64);
+      else dot2(st, P, a[k]->data, a[k]->data, nullptr, half, part, nullptr, nbl64);
+      finish(st, part, nullptr, nbl64, scal, FIN_STORE, SLOT_TMP);
+      read_scalars(h, st);
+      v[k] = h->h_scal[SLOT_TMP];
+    }
+    const double pn = v[2] + v[3];
+    *full_resid = pn > 0 ? std::sqrt((v[0] + v[1]) / pn) : 0.0;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return status;
+}
+
+// --------------------------------------------------------------------------
 // Batched solve: nrhs right-hand sides on one gauge field, every kernel of
 // an iteration launched once for all of them.  The iteration's decisions are
 // taken on the device (ctl_*), masks drop finished RHS from every launch, and
@@ -1326,8 +1387,8 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
     stage.ensure(canon);
     h->upload(stage.p, U, canon, st);
     auto g = std::make_shared<mspcg_ctx::GaugeStore>();
-    g->g64.ensure((size_t)V * 4 * 9 * sizeof(double2));
-    g->g32.ensure((size_t)V * 4 * 9 * sizeof(float2));
+    g->g64.ensure((size_t)V * 4 * 10 * sizeof(double2));
+    g->g32.ensure((size_t)V * 4 * 10 * sizeof(float2));
     pack_gauge(st, g->g64.p, true, stage.as<double>(), h->lat);
     pack_gauge(st, g->g32.p, false, stage.as<double>(), h->lat);
     h->gs = g;
@@ -1454,6 +1515,17 @@ mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0
     mspcg_status r = solve_impl(h, db.as<double>(), dx.as<double>(), x0 ? dx0.as<double>() : nullptr, h->stream, st);
     h->download(x, dx.p, bytes, h->stream);
     return r;
+  });
+}
+
+mspcg_status mspcg_solve_full_device(mspcg_t h, const double* phi, double* psi, void* hip_stream, mspcg_stats* st,
+                                     double* full_rel_resid) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !phi || !psi) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    need_state(h);
+    h->ensure_hip();
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
+    return solve_full_impl(h, phi, psi, s, st, full_rel_resid);
   });
 }
 

@@ -315,3 +315,57 @@ def test_profiling_counters():
     s.set_profiling(False)
     assert n0 >= 4 * st.outer_iters and ms0 > 0
     assert n1 == 4 * 3 * st.outer_iters and ms1 > 0
+
+
+# ---------------------------------------------------------------- vector-ALU epilogue
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("Ls,mfma", [(20, True), (12, False)])
+def test_vector_alu_epilogue_paths(prec, Ls, mfma):
+    """The fifth-dimension epilogue on the vector ALUs: always for Ls > 16,
+    and for every Ls with the MFMA engine switched off (mspcg_set_mfma)."""
+    import paper_2104_05615_amd as M
+    dims, sub = (8, 4, 4, 4), (4, 4, 4, 4)
+    U = W.gauge_field(dims, 0.5, 31)
+    op = oracle.MobiusDWF(U, Ls, 1.5, 0.5, 1.8, 0.1)
+    til = oracle.Tiling(dims, sub)
+    psi = rand_field(Ls, op.vh, 33)
+    M.mspcg_set_mfma(1 if mfma else 0)
+    try:
+        s = M.MSPCG(dims)
+        s.load_gauge(U)
+        s.set_mobius(Ls, 1.5, 0.5, 1.8, 0.1)
+        s.set_subdomains(sub)
+        say(f"[gpu] VALU epilogue {prec} Ls={Ls} mfma={mfma}")
+        e = rel(s.apply("A", prec, psi), op.A(psi))
+        assert e < TOL_A[prec], ("A", prec, e)
+        got = s.apply("A_sub", prec, psi)
+        ref = til.prolong(oracle.local_operator(op, til, til.restrict(psi)), op.vh)
+        e = rel(got, ref)
+        assert e < TOL_A[prec], ("A_sub", prec, e)
+        s.close()
+    finally:
+        M.mspcg_set_mfma(1)
+
+
+# ---------------------------------------------------------------- full 5D system
+
+@pytest.mark.parametrize("outer,inner", [("fp64", "fp64"), ("fp32", "fp16")])
+def test_full_five_dimensional_solve(outer, inner):
+    """M psi = phi on both parities through the even-odd Schur complement:
+    the oracle applies the unpreconditioned block operator [[M5, M4_eo],
+    [M4_oe, M5]] to the library's (psi_e, psi_o); the odd half equals the
+    oracle's reconstruction from psi_e."""
+    dims, Ls, sub = (8, 4, 4, 4), 4, (4, 4, 4, 4)
+    s, op, U = setup(dims, Ls, mf=0.05, sub=sub)
+    phi_e, phi_o = rand_field(Ls, op.vh, 51), rand_field(Ls, op.vh, 52)
+    s.set_solver(tol=1e-12, maxiter=4000, inner_iters=4, inner_prec=inner, outer_prec=outer)
+    say(f"[gpu] full 5D solve outer={outer} inner={inner}")
+    psi_e, psi_o, st, res = s.solve_full(phi_e, phi_o)
+    me, mo = op.full(psi_e, psi_o)
+    r = np.sqrt((np.linalg.norm(phi_e - me) ** 2 + np.linalg.norm(phi_o - mo) ** 2)
+                / (np.linalg.norm(phi_e) ** 2 + np.linalg.norm(phi_o) ** 2))
+    say(f"      even solve {st.outer_iters} iterations, full residual oracle {r:.2e} library {res:.2e}")
+    assert st.status == 0
+    assert r < 1e-9 and abs(r - res) < 1e-11
+    assert rel(psi_o, op.reconstruct_odd(psi_e, phi_o)) < 1e-12
