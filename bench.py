@@ -63,7 +63,7 @@ def stage_bytes(cfg, inner_prec):
     vh = X * Y * Z * T // 2
     Ls = cfg.Ls
     sp32 = 96
-    sp16 = {"fp16": 52, "bf16": 52, "fp32": 96, "fp64": 192}[inner_prec]
+    sp16 = {"int8": 28, "fp16": 52, "bf16": 52, "fp32": 96, "fp64": 192}[inner_prec]
     link = 8 * 18 * 4
     n5 = vh * Ls
     out = {21: 2 * sp32 * n5 + link * vh, 22: 3 * sp32 * n5 + link * vh,
@@ -171,6 +171,9 @@ def serve_stream(volumes, masses, max_rhs, nreq, seed=105, load=0.75, budget_gb=
                 i, t, bufs = pending.pop(0)
             results[i] = srv.wait(t)
             del bufs
+            r = reqs[i]
+            log(f"[serve] request {i} ({r[0]}, mf={r[1]}, {r[2]} RHS) done: status {results[i][0]}, "
+                f"latency {results[i][2] / 1e3:.2f}s")
 
     th = threading.Thread(target=waiter)
     th.start()
@@ -349,9 +352,12 @@ def main():
     ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve", "kernels"])
     ap.add_argument("--log-every", type=int, default=0, help="solver progress line every N outer iterations")
     ap.add_argument("--no-cg64", action="store_true", help="skip the FP64 CG baseline")
+    ap.add_argument("--no-prec-compare", action="store_true",
+                    help="skip the MSPCG solves with the other inner storage formats")
     ap.add_argument("--oracle-check", action="store_true",
                     help="relative residual of the MSPCG solution by the FP64 oracle on the host")
     ap.add_argument("--requests", type=int, default=None, help="serving stream length")
+    ap.add_argument("--budget-gb", type=int, default=200, help="HBM budget of the request server (GB)")
     ap.add_argument("--serve-sample", type=int, default=12,
                     help="requests of the serving sample in solve mode (0: none)")
     args = ap.parse_args()
@@ -364,7 +370,7 @@ def main():
         return kernels_bench(args)
     if args.mode == "serve":
         import torch  # noqa: F401
-        r = serve_stream(nreq=args.requests or 200, **SERVE_FULL)
+        r = serve_stream(nreq=args.requests or 200, budget_gb=args.budget_gb, **SERVE_FULL)
         print(json.dumps({"metric": "serving p50/p99 latency and solves/s", "unit": "s", "value": r["p99_s"],
                           "serve": r}), flush=True)
         return
@@ -444,6 +450,17 @@ def main():
     x_cg = xt.clone()
     sol_rel = float(torch.linalg.vector_norm(x_ms - x_cg) / torch.linalg.vector_norm(x_cg))
 
+    # the preconditioner's storage format against the outer iteration count
+    # (Sec. 3.2: 8-bit storage is cheaper per inner step, 16-bit a better
+    # preconditioner); one solve each, outside the timed region
+    storage = {}
+    for p in ([] if args.no_prec_compare else [q for q in ("fp16", "bf16", "int8") if q != inner]):
+        (dt, st), = run(1, **dict(mspcg_params, inner_prec=p))
+        storage[p] = {"time_s": dt, "outer_iters": st.outer_iters, "status": st.status,
+                      "true_rel_resid": st.true_rel_resid}
+        log(f"[bench] MSPCG inner {p}: {dt:.3f}s, {st.outer_iters} outer iters, "
+            f"true resid {st.true_rel_resid:.2e}")
+
     # roofline of the hop kernels (HIP events over the timed region)
     sbytes, regions = stage_bytes(cfg, inner)
     kernels = {}
@@ -489,6 +506,7 @@ def main():
                     "true_rel_resid": cg32[-1][1].true_rel_resid},
         "cg_fp64": None if args.no_cg64 else {"time_s": cg64[-1][0], "outer_iters": cg64[-1][1].outer_iters,
                                               "true_rel_resid": cg64[-1][1].true_rel_resid},
+        "inner_storage": storage,
         "speedup_vs_cg_fp32": cg32[-1][0] / statistics.median(times),
         ("solution_rel_diff_mspcg_vs_cg32" if args.no_cg64 else "solution_rel_diff_mspcg_vs_cg64"): sol_rel,
         "kernels": kernels,

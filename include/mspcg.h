@@ -57,7 +57,15 @@ typedef enum {
   MSPCG_ERR_BREAKDOWN = -7     /* NaN/Inf or a non-positive curvature in a reduction */
 } mspcg_status;
 
-typedef enum { MSPCG_FP64 = 0, MSPCG_FP32 = 1, MSPCG_FP16 = 2, MSPCG_BF16 = 3 } mspcg_prec;
+/* Storage precisions.  FP16, BF16 and INT8 store the 24 reals of each 5D
+ * site (one colour-spinor) with one FP32 scale per site, the scaled storage
+ * of Sec. 3.2 (value = stored number / limit x scale):
+ *   FP16, BF16  the reals divided by their largest magnitude m, rounded to
+ *               nearest-even in the 16-bit float format; scale m;
+ *   INT8        the integers q = round-half-even(v x (127 / m)) in
+ *               [-127, 127], the product formed in FP32; scale m / 127.
+ * A site of zeros stores zeros with scale 0.  Arithmetic is FP32. */
+typedef enum { MSPCG_FP64 = 0, MSPCG_FP32 = 1, MSPCG_FP16 = 2, MSPCG_BF16 = 3, MSPCG_INT8 = 4 } mspcg_prec;
 
 /* Operators exposed by mspcg_apply (each runs the same kernels the solver runs). */
 typedef enum {
@@ -72,14 +80,15 @@ typedef enum {
   MSPCG_OP_DDAG = 8,          /* D^dag, even                                                     */
   MSPCG_OP_A = 9,             /* A = D^dag D (eq. normal_equation), even                         */
   MSPCG_OP_A_SUB = 10,        /* (+)_s A_s, A_s = R_s A R_s^T with snake terms (eq. diri), even   */
-  MSPCG_OP_PRECOND = 11       /* z = (+)_s CG_k(A_s, r_s), k = inner_iters (Sec. 2.4-2.5), even  */
+  MSPCG_OP_PRECOND = 11,      /* z = (+)_s CG_k(A_s, r_s), k = inner_iters (Sec. 2.4-2.5), even  */
+  MSPCG_OP_STORE = 12         /* the input stored in the given precision and read back (Sec. 3.2) */
 } mspcg_op;
 
 typedef struct {
   double tol;             /* stop at ||b - A x|| / ||b|| <= tol (true residual, FP64)            */
   int32_t maxiter;        /* outer iterations                                                     */
   int32_t inner_iters;    /* k: fixed inner CG iterations per preconditioner application          */
-  mspcg_prec inner_prec;  /* storage of the inner CG: FP64, FP32, FP16 or BF16 (FP32 arithmetic)  */
+  mspcg_prec inner_prec;  /* storage of the inner CG: FP64, FP32, FP16, BF16 or INT8 (FP32 arithmetic) */
   mspcg_prec outer_prec;  /* outer PCG: FP64 or FP32 (FP32 uses FP64 reliable updates)            */
   double reliable_delta;  /* reliable update when ||r|| < delta * max ||r|| since the last one     */
   int32_t beta_rule;      /* 0 = Polak-Ribiere (Sec. 3.2), 1 = Fletcher-Reeves (Alg. 1)            */

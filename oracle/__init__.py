@@ -12,5 +12,5 @@ from .dwf import (  # noqa: F401
     parity_coords, wilson_hop, build_hop_library,
     ptilde, m5_matrix, mphi_matrix, inverse5, adjoint5, apply5, norm2,
     MobiusDWF, Tiling, tiling_ok, local_operator, inner_cg, precondition,
-    pcg, mspcg, cg, SolveInfo,
+    pcg, mspcg, cg, SolveInfo, stored, STORAGE_FORMATS,
 )

@@ -462,3 +462,63 @@ def mspcg(op, tiling, b, k, tol, maxiter, x0=None):
 def cg(op, b, tol, maxiter, x0=None):
     """Plain CG (Alg. 1 with M = 1, Fletcher-Reeves beta)."""
     return pcg(op, b, tol, maxiter, precond=None, beta_rule="FR", x0=x0)
+
+
+# --------------------------------------------------------------------------
+# scaled low-precision storage (Sec. 3.2, fixed-point formats)
+# --------------------------------------------------------------------------
+
+STORAGE_FORMATS = ("fp64", "fp32", "fp16", "bf16", "int8")
+
+
+def stored(psi, fmt):
+    """The value a field takes after it is stored in ``fmt`` and read back.
+
+    Sec. 3.2 stores each colour-spinor (3 colours x 4 spins x complex = 24
+    reals) as small numbers n with one single-precision scale, the value
+    being n / limit x scale.  Readings (the paper fixes no rounding rule,
+    and its 16-bit format is an integer one; here the 16-bit formats are
+    floating point):
+
+    * every real is first rounded to FP32, and m is the largest magnitude of
+      the 24 FP32 reals of the site;
+    * ``fp16`` / ``bf16``: n = the FP32 product v x (1/m) rounded to nearest,
+      ties to even, in the 16-bit float format; limit 1, scale m;
+    * ``int8``: n = v x (127/m), the reciprocal and the product each rounded
+      to FP32, rounded to the nearest integer, ties to even, in [-127, 127];
+      limit 127, scale m;
+    * a site with m = 0 reads back as zeros.
+
+    The read-back value is formed in FP64 from n and m as the definition
+    writes it.  ``fp64`` is the identity and ``fp32`` the rounding of every
+    real to FP32.  ``psi`` is complex with the 4 x 3 spin-colour components
+    in its last two axes.
+    """
+    if fmt not in STORAGE_FORMATS:
+        raise ValueError(fmt)
+    psi = np.asarray(psi, dtype=np.complex128)
+    if fmt == "fp64":
+        return psi.copy()
+    lead = psi.shape[:-2]
+    v = np.stack([psi.real, psi.imag], axis=-1).reshape(lead + (24,))
+    x = v.astype(np.float32)
+    if fmt == "fp32":
+        out = x.astype(np.float64)
+    else:
+        m = np.max(np.abs(x), axis=-1, keepdims=True)
+        safe = np.where(m > 0, m, np.float32(1))
+        if fmt == "int8":
+            inv = np.float32(127) / safe                 # FP32, correctly rounded
+            n = np.clip(np.rint(x * inv), -127, 127)     # rint: ties to even
+            out = n.astype(np.float64) / 127.0 * m.astype(np.float64)
+        else:
+            t = x * (np.float32(1) / safe)               # FP32 product
+            if fmt == "fp16":
+                n = t.astype(np.float16).astype(np.float64)
+            else:
+                import torch
+                n = torch.from_numpy(np.ascontiguousarray(t)).to(torch.bfloat16).to(torch.float64).numpy()
+            out = n * m.astype(np.float64)
+        out = np.where(m > 0, out, 0.0)
+    out = out.reshape(lead + (4, 3, 2))
+    return out[..., 0] + 1j * out[..., 1]

@@ -43,12 +43,13 @@ MSPCG_ERR_OOM = -5
 MSPCG_ERR_HIP = -6
 MSPCG_ERR_BREAKDOWN = -7
 
-MSPCG_FP64, MSPCG_FP32, MSPCG_FP16, MSPCG_BF16 = 0, 1, 2, 3
-PREC = {"fp64": MSPCG_FP64, "fp32": MSPCG_FP32, "fp16": MSPCG_FP16, "bf16": MSPCG_BF16}
+MSPCG_FP64, MSPCG_FP32, MSPCG_FP16, MSPCG_BF16, MSPCG_INT8 = 0, 1, 2, 3, 4
+PREC = {"fp64": MSPCG_FP64, "fp32": MSPCG_FP32, "fp16": MSPCG_FP16, "bf16": MSPCG_BF16, "int8": MSPCG_INT8}
 
 OPS = {
     "dslash_eo": 0, "dslash_oe": 1, "dslash_dag_eo": 2, "dslash_dag_oe": 3,
     "m5": 4, "m5inv": 5, "mphi": 6, "D": 7, "Ddag": 8, "A": 9, "A_sub": 10, "precond": 11,
+    "store": 12,
 }
 
 KERNEL_OUTER_HOP, KERNEL_INNER_HOP, KERNEL_PRECOND, KERNEL_OUTER_HOP64 = 0, 1, 2, 3

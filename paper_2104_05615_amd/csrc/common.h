@@ -40,10 +40,16 @@ template <> struct StoreTraits<__hip_bfloat16> {
   using chunk = uint4; static constexpr int nchunk = 3; using calc = float; static constexpr bool scaled = true;
 };
 
+// 8-bit fixed point: a site's 24 reals as int8 in [-127, 127] (three 8-byte
+// chunks) times one FP32 scale (the largest magnitude / 127)
+template <> struct StoreTraits<int8_t> {
+  using chunk = uint2; static constexpr int nchunk = 3; using calc = float; static constexpr bool scaled = true;
+};
+
 template <typename S> struct Field {
   using chunk = typename StoreTraits<S>::chunk;
   chunk* data;     // nchunk arrays of `stride` chunks
-  float* scale;    // 16-bit formats only
+  float* scale;    // scaled formats (16- and 8-bit) only
   int64_t stride;
   // right-hand side r of a batch stored one whole field after another
   __device__ __forceinline__ Field at(int r) const {
@@ -61,6 +67,27 @@ __device__ __forceinline__ uint32_t word(const uint4& c, int j) {
 }
 __device__ __forceinline__ float half_lo(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
 __device__ __forceinline__ float half_hi(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
+
+// eight int8 values of a 64-bit chunk, sign-extended with shifts
+__device__ __forceinline__ void unpack8_i8(const uint2& c, float* v) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t w = k < 4 ? c.x : c.y;
+    const int sh = 8 * (k & 3);
+    v[k] = (float)(((int)(w << (24 - sh))) >> 24);
+  }
+}
+// eight values in [-127.5, 127.5] rounded to int8
+__device__ __forceinline__ uint2 pack8_i8(const float* v) {
+  uint32_t w[2] = {0u, 0u};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int q = __float2int_rn(v[k]);
+    q = q > 127 ? 127 : (q < -127 ? -127 : q);
+    w[k >> 2] |= ((uint32_t)q & 0xffu) << (8 * (k & 3));
+  }
+  return make_uint2(w[0], w[1]);
+}
 
 template <typename S> __device__ __forceinline__ void unpack8(const uint4& c, float* v);
 template <> __device__ __forceinline__ void unpack8<__half>(const uint4& c, float* v) {
@@ -150,6 +177,17 @@ __device__ __forceinline__ void load_site(const Field<S>& f, uint32_t i, T* v) {
       v[4 * k] = __uint_as_float(c.x); v[4 * k + 1] = __uint_as_float(c.y);
       v[4 * k + 2] = __uint_as_float(c.z); v[4 * k + 3] = __uint_as_float(c.w);
     }
+  } else if constexpr (std::is_same<S, int8_t>::value) {
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+    const float sc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
+    float tmp[24];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(r, off + k * cs, 0, 0);
+      unpack8_i8(make_uint2(c.x, c.y), tmp + 8 * k);
+    }
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = tmp[k] * sc;
   } else {
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
     const float sc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
@@ -189,6 +227,23 @@ __device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const 
       c.z = __float_as_uint((float)v[4 * k + 2]); c.w = __float_as_uint((float)v[4 * k + 3]);
       __builtin_amdgcn_raw_buffer_store_b128(c, r, off + k * cs, 0, 0);
     }
+  } else if constexpr (std::is_same<S, int8_t>::value) {
+    float mx = 0.f;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) mx = fmaxf(mx, fabsf((float)v[k]));
+    const float inv = mx > 0.f ? 127.0f / mx : 0.f;
+    float tmp[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) tmp[k] = (float)v[k] * inv;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint2 q = pack8_i8(tmp + 8 * k);
+      u32x2 c;
+      c.x = q.x; c.y = q.y;
+      __builtin_amdgcn_raw_buffer_store_b64(c, r, off + k * cs, 0, 0);
+    }
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(mx * (1.0f / 127.0f)), rs, i * 4u, 0, 0);
   } else {
     float mx = 0.f;
 #pragma unroll
@@ -209,7 +264,7 @@ __device__ __forceinline__ void store_site(const Field<S>& f, uint32_t i, const 
   }
 }
 
-// As load_site, but 16-bit formats return the stored values without their
+// As load_site, but the scaled formats return the stored values without their
 // scale, which is returned instead (1 for FP32/FP64): a hop is linear, so
 // the scale is applied once, in the final accumulate.
 template <typename S, typename T>
@@ -217,6 +272,19 @@ __device__ __forceinline__ T load_site_unscaled(const Field<S>& f, uint32_t i, T
   if constexpr (!StoreTraits<S>::scaled) {
     load_site(f, i, v);
     return (T)1;
+  } else if constexpr (std::is_same<S, int8_t>::value) {
+    using C = typename Field<S>::chunk;
+    const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+    const uint32_t off = i * (uint32_t)sizeof(C);
+    const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+    const float sc = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(r, off + k * cs, 0, 0);
+      unpack8_i8(make_uint2(c.x, c.y), v + 8 * k);
+    }
+    return sc;
   } else {
     using C = typename Field<S>::chunk;
     const __amdgpu_buffer_rsrc_t r = field_rsrc(f);

@@ -8,7 +8,7 @@
 
 namespace mspcg {
 
-enum class Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+enum class Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, I8 = 4 };
 
 // A single-parity 5D field in device memory, type-erased.
 struct FieldPtr {

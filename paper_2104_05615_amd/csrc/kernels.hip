@@ -122,6 +122,7 @@ void hop_full(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, c
     case Prec::F32: hop_full_t<float>(st, out, in, w, gauge, geo, dagger, epi, bt, sc); break;
     case Prec::F16: hop_full_t<__half>(st, out, in, w, gauge, geo, dagger, epi, bt, sc); break;
     case Prec::BF16: hop_full_t<__hip_bfloat16>(st, out, in, w, gauge, geo, dagger, epi, bt, sc); break;
+    case Prec::I8: hop_full_t<int8_t>(st, out, in, w, gauge, geo, dagger, epi, bt, sc); break;
   }
 }
 
@@ -150,6 +151,7 @@ void hop_sub(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, co
     case Prec::BF16:
       hop_sub_t<__hip_bfloat16>(st, out, in, w, gauge, lat, out_parity, tb, nsub, Ls, dagger, epi, bt, sc);
       break;
+    case Prec::I8: hop_sub_t<int8_t>(st, out, in, w, gauge, lat, out_parity, tb, nsub, Ls, dagger, epi, bt, sc); break;
   }
 }
 
@@ -235,6 +237,7 @@ void apply5_full(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& w,
     case Prec::F32: apply5_t<float>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial, bt); break;
     case Prec::F16: apply5_t<__half>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial, bt); break;
     case Prec::BF16: apply5_t<__hip_bfloat16>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial, bt); break;
+    case Prec::I8: apply5_t<int8_t>(st, out, w, nullptr, nullptr, -1, E, nsites, Ls, norm_partial, bt); break;
   }
 }
 
@@ -300,6 +303,9 @@ void pack_field(hipStream_t st, const FieldPtr& out, const double* canon, int64_
       hipLaunchKernelGGL(k_pack<__hip_bfloat16>, grid, block, 0, st, typed<__hip_bfloat16>(out), canon, nsites, Ls,
                          bt.mask);
       break;
+    case Prec::I8:
+      hipLaunchKernelGGL(k_pack<int8_t>, grid, block, 0, st, typed<int8_t>(out), canon, nsites, Ls, bt.mask);
+      break;
   }
   LAUNCH_CHECK();
 }
@@ -320,6 +326,9 @@ void unpack_field(hipStream_t st, double* canon, const FieldPtr& in, int64_t nsi
     case Prec::BF16:
       hipLaunchKernelGGL(k_unpack<__hip_bfloat16>, grid, block, 0, st, canon, typed<__hip_bfloat16>(in), nsites, Ls,
                          bt.mask);
+      break;
+    case Prec::I8:
+      hipLaunchKernelGGL(k_unpack<int8_t>, grid, block, 0, st, canon, typed<int8_t>(in), nsites, Ls, bt.mask);
       break;
   }
   LAUNCH_CHECK();

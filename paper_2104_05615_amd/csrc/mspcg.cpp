@@ -86,13 +86,15 @@ Prec to_prec(mspcg_prec p) {
     case MSPCG_FP32: return Prec::F32;
     case MSPCG_FP16: return Prec::F16;
     case MSPCG_BF16: return Prec::BF16;
+    case MSPCG_INT8: return Prec::I8;
   }
   throw Error(MSPCG_ERR_INVALID_ARG, "unknown precision");
 }
 
 int64_t round16(int64_t b) { return (b + 15) / 16 * 16; }
 
-size_t chunk_bytes(Prec p) { return p == Prec::F64 ? 192 : p == Prec::F32 ? 96 : 48; }
+size_t chunk_bytes(Prec p) { return p == Prec::F64 ? 192 : p == Prec::F32 ? 96 : p == Prec::I8 ? 24 : 48; }
+bool scaled(Prec p) { return p == Prec::F16 || p == Prec::BF16 || p == Prec::I8; }
 
 // --------------------------------------------------------------------------
 // fifth-dimension matrices, per chirality (0: P+, 1: P-), Ls x Ls, real.
@@ -407,8 +409,7 @@ struct mspcg_ctx {
     f.stride = n;
     DevBuf& d = buf(key, (size_t)nb * n * chunk_bytes(p));
     f.data = d.p;
-    if (p == Prec::F16 || p == Prec::BF16)
-      f.scale = buf(key + ".scale", (size_t)round16((int64_t)nb * n * sizeof(float))).as<float>();
+    if (scaled(p)) f.scale = buf(key + ".scale", (size_t)round16((int64_t)nb * n * sizeof(float))).as<float>();
     return f;
   }
 
@@ -1252,7 +1253,7 @@ int64_t estimate_solve_bytes(const mspcg_ctx* h, int nrhs) {
   const int Ls = h->Ls;
   auto fbytes = [&](Prec p, int64_t sites5) {
     int64_t b = sites5 * (int64_t)chunk_bytes(p);
-    if (p == Prec::F16 || p == Prec::BF16) b += round16(sites5 * 4);
+    if (scaled(p)) b += round16(sites5 * 4);
     return b;
   };
   int64_t n = 0;
@@ -1322,6 +1323,7 @@ void apply_impl(mspcg_ctx* h, int op, Prec P, const double* in_dev, double* out_
     case MSPCG_OP_D: h->D_op(st, P, fo, fi, "ap"); break;
     case MSPCG_OP_DDAG: h->Ddag_op(st, P, fo, fi, "ap"); break;
     case MSPCG_OP_A: h->A_op(st, P, fo, fi, "ap", nullptr); break;
+    case MSPCG_OP_STORE: fo = fi; break;
     default: throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
   }
   unpack_field(st, out_dev, fo, vh, Ls);
@@ -1621,7 +1623,7 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
                                 void* hip_stream) {
   return guarded([&]() -> mspcg_status {
     if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
-    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_PRECOND) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
+    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
     h->ensure_hip();
@@ -1633,7 +1635,7 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
 mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out) {
   return guarded([&]() -> mspcg_status {
     if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
-    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_PRECOND) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
+    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
     h->ensure_hip();

@@ -278,6 +278,7 @@ static void restrict_o(hipStream_t st, Prec inner, const FieldPtr& r, const Fiel
     case Prec::F32: restrict_t<O, float>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
     case Prec::F16: restrict_t<O, __half>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
     case Prec::BF16: restrict_t<O, __hip_bfloat16>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
+    case Prec::I8: restrict_t<O, int8_t>(st, r, rs, ps, t0, E, lat, tc, nsub, Ls, partial, bt); break;
   }
 }
 
@@ -308,6 +309,7 @@ void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& 
     case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
     case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
     case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
+    case Prec::I8: update_t<int8_t>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
   }
 }
 
@@ -329,6 +331,7 @@ void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& r
     case Prec::F32: xpay5_t<float>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
     case Prec::F16: xpay5_t<__half>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
     case Prec::BF16: xpay5_t<__hip_bfloat16>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
+    case Prec::I8: xpay5_t<int8_t>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
   }
 }
 
@@ -353,6 +356,7 @@ static void prolong_o(hipStream_t st, Prec inner, const FieldPtr& z, const Field
     case Prec::F32: prolong_t<O, float>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
     case Prec::F16: prolong_t<O, __half>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
     case Prec::BF16: prolong_t<O, __hip_bfloat16>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
+    case Prec::I8: prolong_t<O, int8_t>(st, z, zs, r, rold, lat, tc, nsub, Ls, p1, p2, bt); break;
   }
 }
 
