@@ -58,6 +58,15 @@ __device__ __forceinline__ T load_project(const Field<S>& in, uint32_t i, T* h) 
   }
 }
 
+// keep (sc, h) where `keep`, else exact zeros (a select, not a product, so
+// that no value read for an absent neighbour can reach the result)
+template <typename T>
+__device__ __forceinline__ void select_zero(bool keep, T& sc, T* h) {
+  sc = keep ? sc : (T)0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) h[k] = keep ? h[k] : (T)0;
+}
+
 template <int MU, int SIGN, typename S, typename T>
 __device__ __forceinline__ void accumulate(const T* gh, T sc, T* acc) {
   if constexpr (StoreTraits<S>::scaled) reconstruct_fma<MU, SIGN>(gh, sc, acc);
@@ -150,23 +159,26 @@ template <typename T> struct SubGeo {
                                       const int* nb, int s, int Ls, T* acc) const {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
-    T h[12], gh[12], u[18];
+    // A neighbour outside the input region contributes nothing (the cut
+    // of eq. diri).  Its term is still evaluated, on the region's first
+    // site, and then selected away: without a branch around them the loads
+    // of both terms of the direction are in flight together.
     const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
-    if (jf >= 0) {
-      const T sc = load_project<MU, SF>(in, (base_in + (uint32_t)jf) * (uint32_t)Ls + (uint32_t)s, h);
-      load_link(g, par, MU, lx >> 1, u);
-      su3_mul_half<false>(u, h, gh);
-      accumulate<MU, SF, S>(gh, sc, acc);
-    }
-    if (jb >= 0) {
-      const int L = lat.ext(MU);
-      const uint32_t st = lat.stride(MU);
-      const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
-      const T sc = load_project<MU, SB>(in, (base_in + (uint32_t)jb) * (uint32_t)Ls + (uint32_t)s, h);
-      load_link(g, 1 - par, MU, lb >> 1, u);
-      su3_mul_half<true>(u, h, gh);
-      accumulate<MU, SB, S>(gh, sc, acc);
-    }
+    const bool hf = jf >= 0, hb = jb >= 0;
+    const int L = lat.ext(MU);
+    const uint32_t st = lat.stride(MU);
+    const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
+    T h[12], gh[12], u[18];
+    T sc = load_project<MU, SF>(in, (base_in + (uint32_t)(hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s, h);
+    select_zero(hf, sc, h);
+    load_link(g, par, MU, lx >> 1, u);
+    su3_mul_half<false>(u, h, gh);
+    accumulate<MU, SF, S>(gh, sc, acc);
+    sc = load_project<MU, SB>(in, (base_in + (uint32_t)(hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s, h);
+    select_zero(hb, sc, h);
+    load_link(g, 1 - par, MU, lb >> 1, u);
+    su3_mul_half<true>(u, h, gh);
+    accumulate<MU, SB, S>(gh, sc, acc);
   }
 
   template <bool DAG, typename S>
@@ -262,14 +274,20 @@ template <typename S> struct UsesMfma {
   static constexpr bool half_ops = StoreTraits<S>::scaled;   // FP16 operands with column scales
 };
 
+// Every operand below is read at a clamped index, always inside its array,
+// and then selected to zero where it lies outside the Ls x Ls block: with no
+// branch around them the loads of all operands are in flight together.
+
 // A operands (the matrix) for one chirality: f16 path
 __device__ __forceinline__ half4_t mfma_a16(const float* E, int chi, int Ls, int lane) {
   const int i = lane & 15, g = lane >> 4;
+  const int ic = i < Ls ? i : Ls - 1;
   half4_t a;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int t = 4 * g + v;
-    a[v] = (i < Ls && t < Ls) ? (_Float16)E[(chi * Ls + i) * Ls + t] : (_Float16)0.f;
+    const float e = E[(chi * Ls + ic) * Ls + (t < Ls ? t : Ls - 1)];
+    a[v] = (i < Ls && t < Ls) ? (_Float16)e : (_Float16)0.f;
   }
   return a;
 }
@@ -282,20 +300,38 @@ __device__ __forceinline__ float4_t mfma_tile16(half4_t a, const float* tile, in
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int t = 4 * g + v;
-    b[v] = t < Ls ? (_Float16)(tile[col * stride + t * 24 + q] * ics) : (_Float16)0.f;
+    const float x = tile[col * stride + (t < Ls ? t : Ls - 1) * 24 + q];
+    b[v] = t < Ls ? (_Float16)(x * ics) : (_Float16)0.f;
   }
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
 }
 
-__device__ __forceinline__ float4_t mfma_tile32(const float* E, int chi, const float* tile, int stride, int Ls, int q,
-                                                int lane, float4_t acc) {
+// A operands for one chirality: f32 path (four k-steps of 16x16x4)
+struct A32 {
+  float a[4];
+};
+__device__ __forceinline__ A32 mfma_a32(const float* E, int chi, int Ls, int lane) {
+  const int col = lane & 15, g = lane >> 4;
+  const int cc = col < Ls ? col : Ls - 1;
+  A32 r;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int t = 4 * kk + g;
+    const float e = E[(chi * Ls + cc) * Ls + (t < Ls ? t : Ls - 1)];
+    r.a[kk] = (col < Ls && t < Ls) ? e : 0.f;
+  }
+  return r;
+}
+
+__device__ __forceinline__ float4_t mfma_tile32(const A32& a, const float* tile, int stride, int Ls, int q, int lane,
+                                                float4_t acc) {
   const int col = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int t = 4 * kk + g;
-    const float a = (col < Ls && t < Ls) ? E[(chi * Ls + col) * Ls + t] : 0.f;
-    const float b = t < Ls ? tile[col * stride + t * 24 + q] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    const float x = tile[col * stride + (t < Ls ? t : Ls - 1) * 24 + q];
+    const float b = t < Ls ? x : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], b, acc, 0, 0, 0);
   }
   return acc;
 }
@@ -389,15 +425,21 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   T* myA = tileA + sl * tile_stride(Ls);
   T* myB = tileB + sl * tile_stride(Ls);
   if (inb) tile_put(myA, s, h);
+  // centre field and the fused dot's field: read without a branch (index 0
+  // where there is nothing to read, then zeros selected), so that their loads
+  // are in flight with the last direction of the hop and with the epilogue.
+  // FP64 keeps the branch: it has no registers to spare for the overlap.
+  constexpr bool early = sizeof(T) == 4;
   T wv[24];
   if (HASW) {
-    if (valid && r.w5 >= 0) load_site(w, r.w5, wv);
-    else {
+    const bool hw = valid && r.w5 >= 0;
+    if (early || hw) load_site(w, hw ? (uint32_t)r.w5 : 0u, wv);
 #pragma unroll
-      for (int k = 0; k < 24; ++k) wv[k] = 0;
-    }
+    for (int k = 0; k < 24; ++k) wv[k] = hw ? wv[k] : (T)0;
     if (e0_dense && inb) tile_put(myB, s, wv);
   }
+  T pv[24];
+  if (early && dot_partial) load_site(dotf, valid ? (uint32_t)r.out5 : 0u, pv);
 
   if constexpr (MF) {
     constexpr bool HO = UsesMfma<S>::half_ops;
@@ -422,11 +464,15 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
     }
     if (E1 || e0_dense) {
       half4_t a1[2], a0[2];
-      if (HO) {
+      A32 f1[2], f0[2];
 #pragma unroll
-        for (int chi = 0; chi < 2; ++chi) {
+      for (int chi = 0; chi < 2; ++chi) {
+        if (HO) {
           if (E1) a1[chi] = mfma_a16((const float*)E1, chi, Ls, lane);
           if (e0_dense) a0[chi] = mfma_a16((const float*)E0, chi, Ls, lane);
+        } else {
+          if (E1) f1[chi] = mfma_a32((const float*)E1, chi, Ls, lane);
+          if (e0_dense) f0[chi] = mfma_a32((const float*)E0, chi, Ls, lane);
         }
       }
       auto tile = [&](int q) {
@@ -436,8 +482,8 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
           if (E1) acc = mfma_tile16(a1[chi], (const float*)tileA, tile_stride(Ls), Ls, q, ics, lane, acc);
           if (e0_dense) acc = mfma_tile16(a0[chi], (const float*)tileB, tile_stride(Ls), Ls, q, ics, lane, acc);
         } else {
-          if (E1) acc = mfma_tile32((const float*)E1, chi, (const float*)tileA, tile_stride(Ls), Ls, q, lane, acc);
-          if (e0_dense) acc = mfma_tile32((const float*)E0, chi, (const float*)tileB, tile_stride(Ls), Ls, q, lane, acc);
+          if (E1) acc = mfma_tile32(f1[chi], (const float*)tileA, tile_stride(Ls), Ls, q, lane, acc);
+          if (e0_dense) acc = mfma_tile32(f0[chi], (const float*)tileB, tile_stride(Ls), Ls, q, lane, acc);
         }
         return acc;
       };
@@ -502,8 +548,7 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   if (dot_partial) {
     T loc = 0;
     if (valid) {
-      T pv[24];
-      load_site(dotf, r.out5, pv);
+      if (!early) load_site(dotf, r.out5, pv);
 #pragma unroll
       for (int k = 0; k < 24; ++k) loc += pv[k] * y[k];
     }
