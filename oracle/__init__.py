@@ -13,4 +13,6 @@ from .dwf import (  # noqa: F401
     ptilde, m5_matrix, mphi_matrix, inverse5, adjoint5, apply5, norm2,
     MobiusDWF, Tiling, tiling_ok, local_operator, inner_cg, precondition,
     pcg, mspcg, cg, SolveInfo, stored, STORAGE_FORMATS,
+    transform, transform_dag, local_op_full, reduced_precondition, outer_sum, chi2,
+    quartic_line_min, train_transform,
 )

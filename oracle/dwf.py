@@ -522,3 +522,111 @@ def stored(psi, fmt):
         out = np.where(m > 0, out, 0.0)
     out = out.reshape(lead + (4, 3, 2))
     return out[..., 0] + 1j * out[..., 1]
+
+
+# --------------------------------------------------------------------------
+# reduced-Ls preconditioner (Sec. 3.3)
+# --------------------------------------------------------------------------
+
+
+def transform(Tm, v):
+    """[T v](s, x, mu, c) = sum_{t, nu} T[s, mu, t, nu] v(t, x, nu, c).
+
+    Sec. 3.3: T maps a field with Ls slices to one with Lhat slices, mixes
+    spin and the fifth dimension and is the identity in colour and on the
+    4D sites.  ``Tm`` has shape (Lhat, 4, Ls, 4), ``v`` (..., Ls, V/2, 4, 3)."""
+    return np.einsum("smtn,...txnc->...sxmc", Tm, v)
+
+
+def transform_dag(Tm, w):
+    """T^dag w, with [T^dag]_{t nu, s mu} = conj(T_{s mu, t nu})."""
+    return np.einsum("smtn,...sxmc->...txnc", Tm.conj(), w)
+
+
+def local_op_full(op, tiling, v):
+    """(+)_s A_s applied to a full even field: every subdomain's part through
+    its own local operator, the results put back in place."""
+    return tiling.prolong(local_operator(op, tiling, tiling.restrict(v)), op.vh)
+
+
+def reduced_precondition(op_hat, tiling, Tm, mu, r, k, inverse=None):
+    """z = (T^dag Mhat^-1 T + mu 1) r (Sec. 3.3), where Mhat^-1 is the k-step
+    inner CG on the reduced-Ls local operator (+)_s Ahat_s, exactly as the
+    full-Ls preconditioner applies M^-1.  ``inverse`` replaces Mhat^-1 by a
+    given linear map (used by the gradient checks)."""
+    rh = transform(Tm, r)
+    zh = inverse(rh) if inverse is not None else precondition(op_hat, tiling, rh, k)
+    return transform_dag(Tm, zh) + mu * r
+
+
+def outer_sum(f, g):
+    """G[s, mu, t, nu] = sum over 4D sites and colour of f(s, x, mu, c) conj(g(t, x, nu, c))."""
+    return np.einsum("...sxmc,...txnc->smtn", f, g.conj())
+
+
+def chi2(op, op_hat, tiling, Tm, mu, vs, k, inverse=None, gradient=False):
+    """Training loss of Sec. 3.3 and its gradient with respect to T.
+
+    chi^2 = sum_i |M (T^dag Mhat^-1 T + mu) v_i - v_i|^2 with M = (+)_s A_s,
+    the operator whose k-step inverse the full-Ls preconditioner applies.
+
+    Gradient (derived here; the paper states that it is analytic): with
+    H = Mhat^-1 taken as a Hermitian linear map, e_i the residual above,
+    m_i = M e_i, b_i = H T v_i and a_i = H T m_i,
+        d chi^2 / d Re T + i d chi^2 / d Im T
+            = 2 sum_i [ outer_sum(b_i, m_i) + outer_sum(a_i, v_i) ].
+    With the k-step CG as H (not linear in its input) this is the gradient
+    of the linearised loss, which the training uses as its direction."""
+    Hinv = inverse if inverse is not None else (lambda x: precondition(op_hat, tiling, x, k))
+    total = 0.0
+    g = np.zeros_like(Tm, dtype=np.complex128)
+    for v in vs:
+        b = Hinv(transform(Tm, v))
+        e = local_op_full(op, tiling, transform_dag(Tm, b) + mu * v) - v
+        total += norm2(e)
+        if gradient:
+            m = local_op_full(op, tiling, e)
+            a = Hinv(transform(Tm, m))
+            g += 2.0 * (outer_sum(b, m) + outer_sum(a, v))
+    return (total, g) if gradient else total
+
+
+def quartic_line_min(f, d_scale):
+    """Minimiser over eta >= 0 of the quartic through f at eta = j d_scale,
+    j = 0..4 (exact when f is a quartic, as chi^2 along a line is for a
+    linear Mhat^-1).  Returns (eta, f(eta) predicted by the fit)."""
+    etas = d_scale * np.arange(5.0)
+    vals = np.array([f(e) for e in etas])
+    c = np.polyfit(etas, vals, 4)
+    roots = np.roots(np.polyder(c))
+    cand = [0.0] + [r.real for r in roots if abs(r.imag) < 1e-12 * max(1.0, abs(r)) and r.real > 0]
+    best = min(cand, key=lambda e: np.polyval(c, e))
+    return best, float(np.polyval(c, best)), vals
+
+
+def train_transform(op, op_hat, tiling, T0, mu, vs, k, iters, momentum=0.5, step0=1e-3, inverse=None):
+    """Train T by line search along a momentum direction (Sec. 3.3).
+
+    Readings (the paper names the two methods only): search direction
+    d_j = -g_j + momentum * d_{j-1} (d_{-1} = 0), g_j the gradient of
+    ``chi2``; T_{j+1} = T_j + eta_j d_j with eta_j the minimiser over eta >= 0
+    of the quartic through chi^2 at eta = 0, s, 2s, 3s, 4s along d_j, where s
+    is the previous step eta_{j-1}, or step0 / |d_j| when there is none (first
+    iteration, or a zero step).  Returns T and the chi^2 history."""
+    T = np.array(T0, dtype=np.complex128)
+    d_prev = np.zeros_like(T)
+    hist = [chi2(op, op_hat, tiling, T, mu, vs, k, inverse)]
+    eta_prev = 0.0
+    for _ in range(iters):
+        _, g = chi2(op, op_hat, tiling, T, mu, vs, k, inverse, gradient=True)
+        d = -g + momentum * d_prev
+        dn = float(np.linalg.norm(d))
+        if dn == 0.0:
+            break
+        s = eta_prev if eta_prev > 0 else step0 / dn
+        eta, _, _ = quartic_line_min(lambda e: chi2(op, op_hat, tiling, T + e * d, mu, vs, k, inverse), s)
+        T = T + eta * d
+        d_prev = d
+        eta_prev = eta
+        hist.append(chi2(op, op_hat, tiling, T, mu, vs, k, inverse))
+    return T, hist
