@@ -360,15 +360,22 @@ __device__ __forceinline__ float half_at(const uint4* q, int k) {
   return (k & 1) ? half_hi(w) : half_lo(w);
 }
 
+//
+// Each output is one v_fma_mix_f32 on the two stored halves: the unit
+// multiplier is hidden from the compiler, which would otherwise fold the
+// product away and convert both halves separately before an FP32 add.  The
+// result is the same FP32 number (the conversions are exact, the sum is
+// rounded once either way).
 template <int MU, int SIGN>
 __device__ __forceinline__ void project_h(const uint4* q, float* h) {
+  float S = (float)SIGN;
+  asm volatile("" : "+v"(S));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float u0r = half_at(q, (0 * 3 + c) * 2), u0i = half_at(q, (0 * 3 + c) * 2 + 1);
     const float u1r = half_at(q, (1 * 3 + c) * 2), u1i = half_at(q, (1 * 3 + c) * 2 + 1);
     const float d2r = half_at(q, (2 * 3 + c) * 2), d2i = half_at(q, (2 * 3 + c) * 2 + 1);
     const float d3r = half_at(q, (3 * 3 + c) * 2), d3i = half_at(q, (3 * 3 + c) * 2 + 1);
-    constexpr float S = (float)SIGN;
     float h0r, h0i, h1r, h1i;
     if constexpr (MU == 0) {
       h0r = __builtin_fmaf(S, d3i, u0r); h0i = __builtin_fmaf(-S, d3r, u0i);

@@ -240,6 +240,45 @@ HostTables build_tables(const int* dims, const int* sub) {
           if (dist <= 1 && par == 1) { H.N1.index[bi] = (int)H.N1.coords.size(); H.N1.coords.push_back(c); }
           if (dist <= 2 && par == 0) { H.N2.index[bi] = (int)H.N2.coords.size(); H.N2.coords.push_back(c); }
         }
+  // Order N1 and N2 by which neighbours their producing hop finds in its
+  // input region (h1: N1 <- C, h2: N2 <- N1; stable, so box order within a
+  // pattern): sites at the region's rim have one or two of the eight, and a
+  // wavefront then holds sites of one pattern and skips the absent terms.
+  auto wrap_or_outside = [&](int* n, int mu) {
+    if (!part[mu]) n[mu] = (n[mu] + dims[mu]) % dims[mu];
+    else if (n[mu] < lo[mu] || n[mu] >= lo[mu] + ext[mu]) return true;
+    return false;
+  };
+  auto presence = [&](const short4& c, const Region& in) {
+    int mask = 0;
+    for (int mu = 0; mu < 4; ++mu)
+      for (int dir = 0; dir < 2; ++dir) {
+        int n[4] = {c.x, c.y, c.z, c.w};
+        n[mu] += dir == 0 ? 1 : -1;
+        if (!wrap_or_outside(n, mu) && in.index[box_index(n)] >= 0) mask |= 1 << (2 * mu + dir);
+      }
+    return mask;
+  };
+  auto reorder = [&](Region& R, const Region& in) {
+    const size_t n = R.coords.size();
+    std::vector<int> key(n), order(n);
+    for (size_t j = 0; j < n; ++j) {
+      key[j] = presence(R.coords[j], in);
+      order[j] = (int)j;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<short4> coords(n);
+    for (size_t j = 0; j < n; ++j) {
+      coords[j] = R.coords[order[j]];
+      const short4 c = coords[j];
+      int l2[4] = {c.x, c.y, c.z, c.w};
+      R.index[box_index(l2)] = (int)j;
+    }
+    R.coords.swap(coords);
+  };
+  reorder(H.N1, H.C);
+  reorder(H.N2, H.N1);
+
   auto neighbours = [&](const Region& out, const Region& in) {
     std::vector<int> nb(out.coords.size() * 8, -1);
     for (size_t j = 0; j < out.coords.size(); ++j) {
@@ -248,8 +287,7 @@ HostTables build_tables(const int* dims, const int* sub) {
         for (int dir = 0; dir < 2; ++dir) {
           int n[4] = {c.x, c.y, c.z, c.w};
           n[mu] += dir == 0 ? 1 : -1;
-          if (!part[mu]) n[mu] = (n[mu] + dims[mu]) % dims[mu];
-          else if (n[mu] < lo[mu] || n[mu] >= lo[mu] + ext[mu]) continue;
+          if (wrap_or_outside(n, mu)) continue;
           nb[j * 8 + 2 * mu + dir] = in.index[box_index(n)];
         }
     }

@@ -58,15 +58,6 @@ __device__ __forceinline__ T load_project(const Field<S>& in, uint32_t i, T* h) 
   }
 }
 
-// keep (sc, h) where `keep`, else exact zeros (a select, not a product, so
-// that no value read for an absent neighbour can reach the result)
-template <typename T>
-__device__ __forceinline__ void select_zero(bool keep, T& sc, T* h) {
-  sc = keep ? sc : (T)0;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) h[k] = keep ? h[k] : (T)0;
-}
-
 template <int MU, int SIGN, typename S, typename T>
 __device__ __forceinline__ void accumulate(const T* gh, T sc, T* acc) {
   if constexpr (StoreTraits<S>::scaled) reconstruct_fma<MU, SIGN>(gh, sc, acc);
@@ -160,25 +151,46 @@ template <typename T> struct SubGeo {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     // A neighbour outside the input region contributes nothing (the cut
-    // of eq. diri).  Its term is still evaluated, on the region's first
-    // site, and then selected away: without a branch around them the loads
-    // of both terms of the direction are in flight together.
+    // of eq. diri).  Both terms' loads are issued without a branch (an
+    // absent neighbour reads the region's first site) so that they are in
+    // flight together; only the arithmetic is guarded.  The regions are
+    // ordered by neighbour pattern, so the guard rarely diverges within a
+    // wavefront and a wavefront of rim sites skips most terms.
     const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
     const bool hf = jf >= 0, hb = jb >= 0;
     const int L = lat.ext(MU);
     const uint32_t st = lat.stride(MU);
     const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
-    T h[12], gh[12], u[18];
-    T sc = load_project<MU, SF>(in, (base_in + (uint32_t)(hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s, h);
-    select_zero(hf, sc, h);
-    load_link(g, par, MU, lx >> 1, u);
-    su3_mul_half<false>(u, h, gh);
-    accumulate<MU, SF, S>(gh, sc, acc);
-    sc = load_project<MU, SB>(in, (base_in + (uint32_t)(hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s, h);
-    select_zero(hb, sc, h);
-    load_link(g, 1 - par, MU, lb >> 1, u);
-    su3_mul_half<true>(u, h, gh);
-    accumulate<MU, SB, S>(gh, sc, acc);
+    if constexpr (sizeof(T) == 8) {
+      // FP64 has no registers for two terms in flight: load under the guard
+      T h[12], gh[12], u[18];
+      if (hf) {
+        const T sc = load_project<MU, SF>(in, (base_in + (uint32_t)jf) * (uint32_t)Ls + (uint32_t)s, h);
+        load_link(g, par, MU, lx >> 1, u);
+        su3_mul_half<false>(u, h, gh);
+        accumulate<MU, SF, S>(gh, sc, acc);
+      }
+      if (hb) {
+        const T sc = load_project<MU, SB>(in, (base_in + (uint32_t)jb) * (uint32_t)Ls + (uint32_t)s, h);
+        load_link(g, 1 - par, MU, lb >> 1, u);
+        su3_mul_half<true>(u, h, gh);
+        accumulate<MU, SB, S>(gh, sc, acc);
+      }
+      return;
+    }
+    T hF[12], hB[12], uF[18], uB[18], gh[12];
+    const T scF = load_project<MU, SF>(in, (base_in + (uint32_t)(hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s, hF);
+    load_link(g, par, MU, lx >> 1, uF);
+    const T scB = load_project<MU, SB>(in, (base_in + (uint32_t)(hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s, hB);
+    load_link(g, 1 - par, MU, lb >> 1, uB);
+    if (hf) {
+      su3_mul_half<false>(uF, hF, gh);
+      accumulate<MU, SF, S>(gh, scF, acc);
+    }
+    if (hb) {
+      su3_mul_half<true>(uB, hB, gh);
+      accumulate<MU, SB, S>(gh, scB, acc);
+    }
   }
 
   template <bool DAG, typename S>
@@ -275,8 +287,11 @@ template <typename S> struct UsesMfma {
 };
 
 // Every operand below is read at a clamped index, always inside its array,
-// and then selected to zero where it lies outside the Ls x Ls block: with no
-// branch around them the loads of all operands are in flight together.
+// so that no branch guards the loads and all of them are in flight together.
+// The A operands (matrix entries) are selected to zero outside the Ls x Ls
+// block; the B operands need no select: rows t >= Ls meet zero A entries,
+// and the clamped read returns row Ls - 1 of the same site column, a value
+// that column's product reads anyway.
 
 // A operands (the matrix) for one chirality: f16 path
 __device__ __forceinline__ half4_t mfma_a16(const float* E, int chi, int Ls, int lane) {
@@ -292,17 +307,29 @@ __device__ __forceinline__ half4_t mfma_a16(const float* E, int chi, int Ls, int
   return a;
 }
 
-// one tile: acc += E_chi H[:, site = lane%16, component q]
-__device__ __forceinline__ float4_t mfma_tile16(half4_t a, const float* tile, int stride, int Ls, int q, float ics,
-                                                int lane, float4_t acc) {
+// Per-lane LDS pointers to the B operand rows of one tile array: row
+// t = 4 (lane / 16) + v of site column lane % 16, clamped to Ls - 1 (for the
+// f16 path; the f32 path reads rows 4 kk + lane / 16).  Computed once, so a
+// tile's reads are these pointers plus the component index.
+struct Rows {
+  const float* p[4];
+};
+__device__ __forceinline__ Rows tile_rows(const float* tile, int stride, int Ls, int lane, bool f16) {
   const int col = lane & 15, g = lane >> 4;
-  half4_t b;
+  Rows r;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int t = 4 * g + v;
-    const float x = tile[col * stride + (t < Ls ? t : Ls - 1) * 24 + q];
-    b[v] = t < Ls ? (_Float16)(x * ics) : (_Float16)0.f;
+    const int t = f16 ? 4 * g + v : 4 * v + g;
+    r.p[v] = tile + col * stride + (t < Ls ? t : Ls - 1) * 24;
   }
+  return r;
+}
+
+// one tile: acc += E_chi H[:, site = lane%16, component q]
+__device__ __forceinline__ float4_t mfma_tile16(half4_t a, const Rows& rows, int q, float ics, float4_t acc) {
+  half4_t b;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) b[v] = (_Float16)(rows.p[v][q] * ics);
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
 }
 
@@ -323,16 +350,9 @@ __device__ __forceinline__ A32 mfma_a32(const float* E, int chi, int Ls, int lan
   return r;
 }
 
-__device__ __forceinline__ float4_t mfma_tile32(const A32& a, const float* tile, int stride, int Ls, int q, int lane,
-                                                float4_t acc) {
-  const int col = lane & 15, g = lane >> 4;
+__device__ __forceinline__ float4_t mfma_tile32(const A32& a, const Rows& rows, int q, float4_t acc) {
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    const int t = 4 * kk + g;
-    const float x = tile[col * stride + (t < Ls ? t : Ls - 1) * 24 + q];
-    const float b = t < Ls ? x : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], b, acc, 0, 0, 0);
-  }
+  for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], rows.p[kk][q], acc, 0, 0, 0);
   return acc;
 }
 
@@ -431,8 +451,9 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   // FP64 keeps the branch: it has no registers to spare for the overlap.
   constexpr bool early = sizeof(T) == 4;
   T wv[24];
+  bool hw = false;
   if (HASW) {
-    const bool hw = valid && r.w5 >= 0;
+    hw = valid && r.w5 >= 0;
     if (early || hw) load_site(w, hw ? (uint32_t)r.w5 : 0u, wv);
 #pragma unroll
     for (int k = 0; k < 24; ++k) wv[k] = hw ? wv[k] : (T)0;
@@ -453,7 +474,12 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
       }
       smax[sl * Ls + s] = m;
     }
-    __syncthreads();
+    // the centre field of a subdomain hop lives on the centre region only,
+    // which the pattern order puts in the last blocks: the other blocks
+    // skip its matrix product
+    bool e0_live = false;
+    if (e0_dense) e0_live = __syncthreads_or(hw ? 1 : 0) != 0;
+    else __syncthreads();
     const int lane = tid & 63, wave = tid >> 6, nwave = (int)(blockDim.x >> 6);
     const int col = lane & 15, g = lane >> 4;
     float cs = 1.f, ics = 1.f;
@@ -469,21 +495,22 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
       for (int chi = 0; chi < 2; ++chi) {
         if (HO) {
           if (E1) a1[chi] = mfma_a16((const float*)E1, chi, Ls, lane);
-          if (e0_dense) a0[chi] = mfma_a16((const float*)E0, chi, Ls, lane);
+          if (e0_live) a0[chi] = mfma_a16((const float*)E0, chi, Ls, lane);
         } else {
           if (E1) f1[chi] = mfma_a32((const float*)E1, chi, Ls, lane);
-          if (e0_dense) f0[chi] = mfma_a32((const float*)E0, chi, Ls, lane);
+          if (e0_live) f0[chi] = mfma_a32((const float*)E0, chi, Ls, lane);
         }
       }
-      auto tile = [&](int q) {
-        const int chi = q / 12;
+      const Rows rA = tile_rows((const float*)tileA, tile_stride(Ls), Ls, lane, HO);
+      const Rows rB = tile_rows((const float*)tileB, tile_stride(Ls), Ls, lane, HO);
+      auto tile = [&](int chi, int q, const Rows& ra, const Rows& rb) {
         float4_t acc = {0.f, 0.f, 0.f, 0.f};
         if (HO) {
-          if (E1) acc = mfma_tile16(a1[chi], (const float*)tileA, tile_stride(Ls), Ls, q, ics, lane, acc);
-          if (e0_dense) acc = mfma_tile16(a0[chi], (const float*)tileB, tile_stride(Ls), Ls, q, ics, lane, acc);
+          if (E1) acc = mfma_tile16(a1[chi], ra, q, ics, acc);
+          if (e0_live) acc = mfma_tile16(a0[chi], rb, q, ics, acc);
         } else {
-          if (E1) acc = mfma_tile32(f1[chi], (const float*)tileA, tile_stride(Ls), Ls, q, lane, acc);
-          if (e0_dense) acc = mfma_tile32(f0[chi], (const float*)tileB, tile_stride(Ls), Ls, q, lane, acc);
+          if (E1) acc = mfma_tile32(f1[chi], ra, q, acc);
+          if (e0_live) acc = mfma_tile32(f0[chi], rb, q, acc);
         }
         return acc;
       };
@@ -494,15 +521,46 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
           if (t < Ls) dst[col * tile_stride(Ls) + t * 24 + q] = (T)(acc[v] * cs);
         }
       };
-      T* dst;
-      if (nwave >= 3) {
-        // at most 8 tiles per wavefront: keep them in registers, then
-        // overwrite the input tile once every wavefront has read it
+      // With three or more wavefronts each holds at most 8 tiles in
+      // registers, then overwrites the input tile once every wavefront has
+      // read it.  For 3 and 4 wavefronts the tile sequence of a wavefront is
+      // fixed at compile time (component q = wave + j * nwave, chirality
+      // j * nwave >= 12), so every LDS access is one base plus an immediate.
+      auto tiles_fixed = [&](auto nwc) {
+        constexpr int NW = decltype(nwc)::value;
+        constexpr int NJ = 24 / NW;
+        const int w = __builtin_amdgcn_readfirstlane(wave);
+        Rows ra = rA, rb = rB;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          ra.p[v] += w;
+          rb.p[v] += w;
+        }
+        float4_t accs[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) accs[j] = tile(j * NW >= 12 ? 1 : 0, j * NW, ra, rb);
+        __syncthreads();
+        T* ob = tileA + col * tile_stride(Ls) + w;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int t = 4 * g + v;
+            if (t < Ls) ob[t * 24 + j * NW] = (T)(accs[j][v] * cs);
+          }
+        }
+      };
+      T* dst = tileA;
+      if (nwave == 3) {
+        tiles_fixed(std::integral_constant<int, 3>());
+      } else if (nwave == 4) {
+        tiles_fixed(std::integral_constant<int, 4>());
+      } else if (nwave > 4) {
         float4_t accs[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int q = wave + j * nwave;
-          if (q < 24) accs[j] = tile(q);
+          if (q < 24) accs[j] = tile(q / 12, q, rA, rB);
         }
         __syncthreads();
 #pragma unroll
@@ -510,9 +568,8 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
           const int q = wave + j * nwave;
           if (q < 24) put(tileA, q, accs[j]);
         }
-        dst = tileA;
       } else {
-        for (int q = wave; q < 24; q += nwave) put(tileO, q, tile(q));
+        for (int q = wave; q < 24; q += nwave) put(tileO, q, tile(q / 12, q, rA, rB));
         dst = tileO;
       }
       __syncthreads();
