@@ -269,6 +269,79 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------- reduced-Ls preconditioner
+
+def reduced_bench(args):
+    """Reduced-Ls preconditioner (Sec. 3.3) on one workload: residual vectors
+    r_k of a full-Ls MSPCG solve (after 25, 50, 100 and 200 outer iterations)
+    train T (Lhat = Ls / 2, started from taking every second slice) for each
+    mu of a small scan, and the full solve then runs with each trained
+    preconditioner; reported beside the full-Ls MSPCG solve."""
+    import torch
+    import workloads as W
+    from workloads.configs import CONFIGS
+    from paper_2104_05615_amd import MSPCG
+    cfg = CONFIGS[args.config]
+    inner = args.inner_prec or cfg.inner_prec
+    U = W.gauge_field(cfg.dims, cfg.eps, cfg.gauge_seed)
+    b = W.gaussian_source(cfg.dims, cfg.Ls, cfg.src_seed)
+    s = MSPCG(cfg.dims)
+    s.load_gauge(U)
+    s.set_mobius(cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
+    s.set_subdomains(cfg.sub)
+    bt = torch.from_numpy(b.view(np.float64).reshape(-1).copy()).cuda()
+    xt = torch.empty_like(bt)
+    n = bt.numel()
+    params = dict(tol=cfg.tol, maxiter=20000, inner_iters=cfg.inner_iters, inner_prec=inner,
+                  outer_prec=cfg.outer_prec)
+
+    def solve(**kw):
+        s.set_solver(**dict(params, **kw))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = s.solve_device(bt.data_ptr(), xt.data_ptr())
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st
+
+    solve()                                      # warm-up
+    t_full, st_full = solve()
+    log(f"[reduced] full Ls={cfg.Ls}: {t_full:.3f}s, {st_full.outer_iters} outer iterations")
+    # training vectors: true residuals b - A x_k of the full-Ls solve
+    vs = []
+    ax = torch.empty_like(bt)
+    for k in (25, 50, 100, 200):
+        solve(maxiter=k)
+        s.apply_device("A", "fp64", xt.data_ptr(), ax.data_ptr())
+        torch.cuda.synchronize()
+        vs.append(bt - ax)
+    V = torch.cat([v / torch.linalg.vector_norm(v) for v in vs]).contiguous()
+    Lh = cfg.Ls // 2
+    T0 = np.zeros((Lh, 4, cfg.Ls, 4), dtype=np.complex128)
+    for j in range(Lh):
+        T0[j, :, 2 * j, :] = np.eye(4)
+    out = {"metric": "reduced-Ls MSPCG time-to-solution @ rel resid 1e-10", "unit": "s", "config": cfg.name,
+           "full": {"Ls": cfg.Ls, "time_s": t_full, "outer_iters": st_full.outer_iters}, "reduced": []}
+    for mu in args.mu:
+        s.set_reduced(Lh, mu=mu, T=T0)
+        s.set_solver(**params)
+        t = time.perf_counter()
+        hist = s.train_reduced(len(vs), V.data_ptr(), args.train_iters, momentum=0.5)
+        t_train = time.perf_counter() - t
+        log(f"[reduced] mu={mu}: trained in {t_train:.1f}s, chi2 {hist[0]:.3e} -> {hist[-1]:.3e}")
+        t_red, st_red = solve(maxiter=5000)
+        s.set_reduced(Lh, mu=mu, T=T0)
+        t_dec, st_dec = solve(maxiter=5000)
+        log(f"[reduced] Lhat={Lh} mu={mu}: chi2 {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f}s; solve "
+            f"{t_red:.3f}s, {st_red.outer_iters} iters (status {st_red.status}); untrained T: {t_dec:.3f}s, "
+            f"{st_dec.outer_iters} iters")
+        out["reduced"].append({"Lhat": Lh, "mu": mu, "train_s": t_train, "chi2_first": hist[0], "chi2_last": hist[-1],
+                               "time_s": t_red, "outer_iters": st_red.outer_iters, "status": st_red.status,
+                               "true_rel_resid": st_red.true_rel_resid,
+                               "untrained": {"time_s": t_dec, "outer_iters": st_dec.outer_iters}})
+    s.set_reduced(0)
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- kernels only (for counter runs)
 
 def kernels_bench(args):
@@ -349,7 +422,9 @@ def main():
     ap.add_argument("--inner-prec", default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve", "kernels"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve", "kernels", "reduced"])
+    ap.add_argument("--mu", type=float, nargs="+", default=[0.05, 0.2], help="mu values of the reduced-Ls scan")
+    ap.add_argument("--train-iters", type=int, default=10, help="training steps of the reduced-Ls transform")
     ap.add_argument("--log-every", type=int, default=0, help="solver progress line every N outer iterations")
     ap.add_argument("--no-cg64", action="store_true", help="skip the FP64 CG baseline")
     ap.add_argument("--no-prec-compare", action="store_true",
@@ -366,6 +441,8 @@ def main():
         sys.exit(2)
     if args.mode == "batch":
         return batch_bench(args)
+    if args.mode == "reduced":
+        return reduced_bench(args)
     if args.mode == "kernels":
         return kernels_bench(args)
     if args.mode == "serve":

@@ -80,7 +80,8 @@ typedef enum {
   MSPCG_OP_DDAG = 8,          /* D^dag, even                                                     */
   MSPCG_OP_A = 9,             /* A = D^dag D (eq. normal_equation), even                         */
   MSPCG_OP_A_SUB = 10,        /* (+)_s A_s, A_s = R_s A R_s^T with snake terms (eq. diri), even   */
-  MSPCG_OP_PRECOND = 11,      /* z = (+)_s CG_k(A_s, r_s), k = inner_iters (Sec. 2.4-2.5), even  */
+  MSPCG_OP_PRECOND = 11,      /* z = (+)_s CG_k(A_s, r_s), k = inner_iters (Sec. 2.4-2.5), even, or the
+                                 reduced-Ls z = (T^dag Mhat^-1 T + mu) r when one is set (Sec. 3.3)  */
   MSPCG_OP_STORE = 12         /* the input stored in the given precision and read back (Sec. 3.2) */
 } mspcg_op;
 
@@ -232,6 +233,44 @@ mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, d
  * Errors: INVALID_ARG (NULL, extents or device differ), NO_GAUGE (src has
  * none). */
 mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src);
+
+/* ---- reduced-Ls preconditioner (Sec. 3.3) ----
+ * z = (T^dag Mhat^-1 T + mu 1) r replaces the preconditioner z = M^-1 r in
+ * every solve and in MSPCG_OP_PRECOND.  Mhat^-1 is the same k-step inner CG
+ * (inner_iters, inner_prec) on the local operator (+)_s Ahat_s of the Mobius
+ * operator with Lhat slices and parameters b_hat, c_hat (M5 and mf as set by
+ * mspcg_set_mobius).  T: host, complex interleaved, [Lhat][4][Ls][4]: row
+ * (s, spin) of the reduced field, column (t, spin) of the full one; the
+ * identity in colour and on the 4D sites; copied.  Lhat = 0 switches back to
+ * the full-Ls preconditioner (T may then be null).  A later mspcg_set_mobius
+ * with another Ls switches it off.  Errors: NO_PARAMS, INVALID_ARG (Lhat
+ * outside [1, Ls], a non-finite value); a singular reduced operator is
+ * reported by the first solve or apply. */
+mspcg_status mspcg_set_reduced(mspcg_t h, int32_t Lhat, double b_hat, double c_hat, double mu, const double* T);
+
+/* The current Lhat (0: off) and, if T is not null and Lhat > 0, a copy of T
+ * (host, complex interleaved, [Lhat][4][Ls][4]). */
+mspcg_status mspcg_get_reduced(mspcg_t h, int32_t* Lhat, double* T);
+
+/* Training loss of Sec. 3.3 over nvec device FP64 fields v (even
+ * checkerboard, one after another):
+ *   chi2 = sum_i |M (T^dag Mhat^-1 T + mu) v_i - v_i|^2,  M = (+)_s A_s,
+ * and, when grad (host, complex interleaved, [Lhat][4][Ls][4]) is not null,
+ * d chi2 / d Re T + i d chi2 / d Im T with Mhat^-1 taken as a linear map.
+ * Arithmetic in outer_prec (FP64 accumulation of sums), the inner solves in
+ * inner_prec.  Errors: INVALID_ARG (no reduced preconditioner, nvec < 1),
+ * NO_GAUGE, NO_PARAMS, BAD_TILING. */
+mspcg_status mspcg_reduced_loss(mspcg_t h, int32_t nvec, const double* v, double* chi2, double* grad);
+
+/* Trains T in place (Sec. 3.3: line search, momentum): iters steps of
+ * d = -grad + momentum d_prev, T += eta d, eta the minimiser over eta >= 0
+ * of chi2(T + eta d), a quartic in eta when Mhat^-1 is taken as linear (as
+ * for the gradient), whose five coefficients are formed exactly from
+ * Mhat^-1 T v_i and Mhat^-1 d v_i.  history (host, iters + 1 entries,
+ * nullable): chi2 before the first step and after each.  Errors as
+ * mspcg_reduced_loss, and INVALID_ARG for iters < 0. */
+mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32_t iters, double momentum,
+                                 double* history);
 
 /* Engine of the fifth-dimension epilogue of the FP32 and 16-bit site kernels
  * with Ls <= 16, for every handle of the process: 1 = MFMA (the default),

@@ -14,5 +14,5 @@ from .dwf import (  # noqa: F401
     MobiusDWF, Tiling, tiling_ok, local_operator, inner_cg, precondition,
     pcg, mspcg, cg, SolveInfo, stored, STORAGE_FORMATS,
     transform, transform_dag, local_op_full, reduced_precondition, outer_sum, chi2,
-    quartic_line_min, train_transform,
+    line_quartic, quartic_min, train_transform,
 )

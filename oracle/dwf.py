@@ -591,42 +591,53 @@ def chi2(op, op_hat, tiling, Tm, mu, vs, k, inverse=None, gradient=False):
     return (total, g) if gradient else total
 
 
-def quartic_line_min(f, d_scale):
-    """Minimiser over eta >= 0 of the quartic through f at eta = j d_scale,
-    j = 0..4 (exact when f is a quartic, as chi^2 along a line is for a
-    linear Mhat^-1).  Returns (eta, f(eta) predicted by the fit)."""
-    etas = d_scale * np.arange(5.0)
-    vals = np.array([f(e) for e in etas])
-    c = np.polyfit(etas, vals, 4)
-    roots = np.roots(np.polyder(c))
-    cand = [0.0] + [r.real for r in roots if abs(r.imag) < 1e-12 * max(1.0, abs(r)) and r.real > 0]
-    best = min(cand, key=lambda e: np.polyval(c, e))
-    return best, float(np.polyval(c, best)), vals
+def line_quartic(op, op_hat, tiling, Tm, d, mu, vs, k, inverse=None):
+    """Coefficients c_0..c_4 of chi^2(T + eta d) = sum_j c_j eta^j with Mhat^-1
+    taken as linear (as the gradient takes it): per vector, with
+    Ha = Mhat^-1 T v and Hb = Mhat^-1 d v,
+        e(eta) = e0 + eta e1 + eta^2 e2,
+        e0 = M (T^dag Ha + mu v) - v,  e1 = M (T^dag Hb + d^dag Ha),  e2 = M d^dag Hb,
+    and chi^2(eta) = sum |e(eta)|^2 expanded in eta."""
+    Hinv = inverse if inverse is not None else (lambda x: precondition(op_hat, tiling, x, k))
+    c = np.zeros(5)
+    for v in vs:
+        ha = Hinv(transform(Tm, v))
+        hb = Hinv(transform(d, v))
+        e0 = local_op_full(op, tiling, transform_dag(Tm, ha) + mu * v) - v
+        e1 = local_op_full(op, tiling, transform_dag(Tm, hb) + transform_dag(d, ha))
+        e2 = local_op_full(op, tiling, transform_dag(d, hb))
+        re = lambda x, y: float(np.vdot(x, y).real)
+        c += [norm2(e0), 2 * re(e0, e1), norm2(e1) + 2 * re(e0, e2), 2 * re(e1, e2), norm2(e2)]
+    return c
 
 
-def train_transform(op, op_hat, tiling, T0, mu, vs, k, iters, momentum=0.5, step0=1e-3, inverse=None):
+def quartic_min(c):
+    """Minimiser over eta >= 0 of sum_j c_j eta^j (c_4 > 0 or lower degree):
+    the best of eta = 0 and the positive real roots of the derivative."""
+    roots = np.roots([4 * c[4], 3 * c[3], 2 * c[2], c[1]]) if c[4] != 0 else np.roots([3 * c[3], 2 * c[2], c[1]])
+    cand = [0.0] + [r.real for r in roots if abs(r.imag) <= 1e-9 * max(1.0, abs(r)) and r.real > 0]
+    val = lambda e: (((c[4] * e + c[3]) * e + c[2]) * e + c[1]) * e + c[0]
+    return min(cand, key=val)
+
+
+def train_transform(op, op_hat, tiling, T0, mu, vs, k, iters, momentum=0.5, inverse=None):
     """Train T by line search along a momentum direction (Sec. 3.3).
 
     Readings (the paper names the two methods only): search direction
     d_j = -g_j + momentum * d_{j-1} (d_{-1} = 0), g_j the gradient of
-    ``chi2``; T_{j+1} = T_j + eta_j d_j with eta_j the minimiser over eta >= 0
-    of the quartic through chi^2 at eta = 0, s, 2s, 3s, 4s along d_j, where s
-    is the previous step eta_{j-1}, or step0 / |d_j| when there is none (first
-    iteration, or a zero step).  Returns T and the chi^2 history."""
+    ``chi2``; T_{j+1} = T_j + eta_j d_j with eta_j the minimiser over
+    eta >= 0 of the quartic ``line_quartic`` (chi^2 along d_j with Mhat^-1
+    taken as linear, exact when it is).  Returns T and the chi^2 history."""
     T = np.array(T0, dtype=np.complex128)
     d_prev = np.zeros_like(T)
     hist = [chi2(op, op_hat, tiling, T, mu, vs, k, inverse)]
-    eta_prev = 0.0
     for _ in range(iters):
         _, g = chi2(op, op_hat, tiling, T, mu, vs, k, inverse, gradient=True)
         d = -g + momentum * d_prev
-        dn = float(np.linalg.norm(d))
-        if dn == 0.0:
+        if not np.any(d):
             break
-        s = eta_prev if eta_prev > 0 else step0 / dn
-        eta, _, _ = quartic_line_min(lambda e: chi2(op, op_hat, tiling, T + e * d, mu, vs, k, inverse), s)
+        eta = quartic_min(line_quartic(op, op_hat, tiling, T, d, mu, vs, k, inverse))
         T = T + eta * d
         d_prev = d
-        eta_prev = eta
         hist.append(chi2(op, op_hat, tiling, T, mu, vs, k, inverse))
     return T, hist

@@ -99,6 +99,10 @@ _SIGS = {
     "mspcg_solve_full_device": [_h, _p, _p, _p, ctypes.POINTER(mspcg_stats), ctypes.POINTER(_d)],
     "mspcg_autotune": [_h, _i32],
     "mspcg_share_gauge": [_h, _h],
+    "mspcg_set_reduced": [_h, _i32, _d, _d, _d, _p],
+    "mspcg_get_reduced": [_h, ctypes.POINTER(_i32), _p],
+    "mspcg_reduced_loss": [_h, _i32, _p, ctypes.POINTER(_d), _p],
+    "mspcg_train_reduced": [_h, _i32, _p, _i32, _d, _p],
     "mspcg_set_graphs": [_h, _i32],
     "mspcg_set_log": [_h, _i32],
     "mspcg_set_mfma": [_i32],
@@ -207,6 +211,7 @@ class MSPCG:
     def set_mobius(self, Ls, b, c, M5, mf):
         _check(mspcg_set_mobius(self._h, int(Ls), float(b), float(c), float(M5), float(mf)))
         self.Ls = int(Ls)
+        self.b, self.c = float(b), float(c)
 
     def set_subdomains(self, sub):
         _check(mspcg_set_subdomains(self._h, (_i32 * 4)(*[int(s) for s in sub])))
@@ -224,6 +229,45 @@ class MSPCG:
 
     def share_gauge(self, other):
         _check(mspcg_share_gauge(self._h, other._h))
+
+    # ---- reduced-Ls preconditioner (Sec. 3.3)
+    def set_reduced(self, Lhat, b_hat=None, c_hat=None, mu=0.0, T=None):
+        """Use z = (T^dag Mhat^-1 T + mu) r as the preconditioner; T complex of shape
+        (Lhat, 4, Ls, 4).  b_hat / c_hat default to this handle's b, c.  Lhat = 0: off."""
+        if int(Lhat) == 0:
+            _check(mspcg_set_reduced(self._h, 0, 0.0, 0.0, 0.0, None))
+            return
+        T = np.ascontiguousarray(np.asarray(T, dtype=np.complex128).reshape(int(Lhat), 4, self.Ls, 4))
+        self._T_keep = T
+        _check(mspcg_set_reduced(self._h, int(Lhat), float(self.b if b_hat is None else b_hat),
+                                 float(self.c if c_hat is None else c_hat), float(mu),
+                                 T.ctypes.data_as(ctypes.c_void_p)))
+
+    def reduced(self):
+        """(Lhat, T) of the current reduced-Ls preconditioner ((0, None) when off)."""
+        L = _i32()
+        _check(mspcg_get_reduced(self._h, ctypes.byref(L), None))
+        if L.value == 0:
+            return 0, None
+        T = np.empty((L.value, 4, self.Ls, 4), dtype=np.complex128)
+        _check(mspcg_get_reduced(self._h, ctypes.byref(L), T.ctypes.data_as(ctypes.c_void_p)))
+        return L.value, T
+
+    def reduced_loss(self, nvec, v_ptr, gradient=False):
+        """chi^2 over nvec device FP64 fields at v_ptr (and its gradient, complex (Lhat, 4, Ls, 4))."""
+        c = _d()
+        L = self.reduced()[0]
+        g = np.empty((L, 4, self.Ls, 4), dtype=np.complex128) if gradient else None
+        _check(mspcg_reduced_loss(self._h, int(nvec), ctypes.c_void_p(v_ptr), ctypes.byref(c),
+                                  g.ctypes.data_as(ctypes.c_void_p) if gradient else None))
+        return (c.value, g) if gradient else c.value
+
+    def train_reduced(self, nvec, v_ptr, iters, momentum=0.5):
+        """Train T in place; returns the chi^2 history (iters + 1 values)."""
+        hist = np.zeros(int(iters) + 1)
+        _check(mspcg_train_reduced(self._h, int(nvec), ctypes.c_void_p(v_ptr), int(iters), float(momentum),
+                                   hist.ctypes.data_as(ctypes.c_void_p)))
+        return hist
 
     def footprint(self, nrhs=1):
         """(bytes a batched solve of nrhs allocates, bytes held now)."""

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "sub.hip", "mspcg.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "sub.hip", "reduced.hip", "mspcg.cpp", "server.cpp"]
 LIB = os.path.join(HERE, "libmspcg.so")
 
 HIPCC_FLAGS = [

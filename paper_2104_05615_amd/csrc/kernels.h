@@ -195,4 +195,23 @@ enum SubFinish { SUB_INIT = 0, SUB_ALPHA, SUB_BETA };
 void sub_finish(hipStream_t st, const double* partial, int bps, int nsub, const SubScalars& sc, int mode,
                 const Batch& bt = Batch());
 
+// ---------------------------------------------------------------- reduced-Ls preconditioner (reduced.hip)
+// out(x, so, mo, c) = sum_{si, mi} W[so][mo][si][mi] in(x, si, mi, c) (+ mu r(x, so, mo, c) when r
+// is given); W complex [Lo][4][Li][4] (double2 for FP64 fields, float2 for FP32).  With p1 set,
+// workgroup partials of Re<out, r> (p1) and Re<out, rold> (p2, when rold is given), indexed
+// [rhs][transform_blocks].
+int transform_sites(int Li, int Lo, Prec p);
+int64_t transform_blocks(int64_t vh, int Li, int Lo, Prec p);
+void transform(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const void* W, int Li, int Lo,
+               int64_t vh, double mu, const FieldPtr* r, const FieldPtr* rold, double* p1, double* p2,
+               const Batch& bt = Batch());
+// e = a - b over nreal reals of one layout, workgroup sums of e^2 in partial[nblocks]
+void diff_norm(hipStream_t st, Prec p, void* e, const void* a, const void* b, int64_t nreal, double* partial,
+               int nblocks);
+// G[(s mf)(t mg)] += sum over sites and colour of f(x, s, mf, c) conj(g(x, t, mg, c)); f has Lf
+// slices, g Lg; partial holds outer_sum_parts(vh) x (Lf 4 Lg 4) entries
+int outer_sum_parts(int64_t vh);
+void outer_sum(hipStream_t st, Prec p, const FieldPtr& f, const FieldPtr& g, int Lf, int Lg, int64_t vh,
+               double2* partial, double2* G);
+
 }  // namespace mspcg

@@ -360,6 +360,15 @@ struct mspcg_ctx {
   char* h_bounce = nullptr;
   static constexpr size_t kBounce = 8u << 20;
 
+  // reduced-Ls preconditioner (Sec. 3.3): z = (T^dag Mhat^-1 T + mu) r.  Lh = 0: off.
+  int Lh = 0;
+  double bh = 0, ch = 0, mu_red = 0;
+  std::vector<double> Tm;                // host, complex interleaved [Lh][4][Ls][4]
+  DevBuf T64, T32, Td64, Td32;           // T and T^dag, double2 / float2
+  DevBuf D64, D32, Dd64, Dd32;           // a training search direction d and d^dag
+  std::unique_ptr<mspcg_ctx> red;        // context at Lh: this handle's gauge field and tiling
+  bool red_dirty = true;
+
   bool profiling = false;
   bool graphs = true;              // batched solves replay captured graphs
   int log_every = 0;               // progress line to stderr every this many outer iterations (0: none)
@@ -465,6 +474,8 @@ struct mspcg_ctx {
     for (const DevBuf* d : {&tb_origin, &tb_cC, &tb_cN1, &tb_cN2, &tb_nbr1, &tb_nbr2, &tb_nbr3, &tb_nbr4, &tb_w2, &tb_w4})
       n += (int64_t)d->n;
     for (auto& kv : ws) n += kv.second ? (int64_t)kv.second->n : 0;
+    n += (int64_t)T64.n + (int64_t)T32.n + (int64_t)Td64.n + (int64_t)Td32.n;
+    if (red) n += red->ws_bytes();
     return n;
   }
 
@@ -490,6 +501,53 @@ struct mspcg_ctx {
   void invalidate_workspace() {
     if (hip_ready) HIPCHK(hipStreamSynchronize(stream));
     ws.clear();
+    red_dirty = true;
+  }
+
+  // ---------------------------------------------------------------- reduced-Ls preconditioner
+  // T and T^dag in both precisions on the device, from the host copy
+  void upload_transform() { upload_matrix(Tm, T64, T32, Td64, Td32); }
+  // a complex [Lh][4][Ls][4] matrix and its adjoint, double2 and float2
+  void upload_matrix(const std::vector<double>& Tm, DevBuf& T64, DevBuf& T32, DevBuf& Td64, DevBuf& Td32) {
+    const int nT = Lh * 4 * Ls * 4;
+    std::vector<double> t64(2 * (size_t)nT), d64(2 * (size_t)nT);
+    for (int s5 = 0; s5 < Lh; ++s5)
+      for (int m = 0; m < 4; ++m)
+        for (int t5 = 0; t5 < Ls; ++t5)
+          for (int n = 0; n < 4; ++n) {
+            const size_t i = ((size_t)(s5 * 4 + m) * Ls + t5) * 4 + n;   // T[s m][t n]
+            const size_t j = ((size_t)(t5 * 4 + n) * Lh + s5) * 4 + m;   // T^dag[t n][s m]
+            t64[2 * i] = Tm[2 * i];
+            t64[2 * i + 1] = Tm[2 * i + 1];
+            d64[2 * j] = Tm[2 * i];
+            d64[2 * j + 1] = -Tm[2 * i + 1];
+          }
+    std::vector<float> t32(t64.begin(), t64.end()), d32(d64.begin(), d64.end());
+    T64.ensure(t64.size() * sizeof(double));
+    Td64.ensure(d64.size() * sizeof(double));
+    T32.ensure(t32.size() * sizeof(float));
+    Td32.ensure(d32.size() * sizeof(float));
+    upload(T64.p, t64.data(), t64.size() * sizeof(double), stream);
+    upload(Td64.p, d64.data(), d64.size() * sizeof(double), stream);
+    upload(T32.p, t32.data(), t32.size() * sizeof(float), stream);
+    upload(Td32.p, d32.data(), d32.size() * sizeof(float), stream);
+  }
+  const void* Tdev(Prec p, bool dag) const {
+    if (p == Prec::F64) return dag ? Td64.p : T64.p;
+    return dag ? Td32.p : T32.p;
+  }
+  const void* Ddev(Prec p, bool dag) const {
+    if (p == Prec::F64) return dag ? Dd64.p : D64.p;
+    return dag ? Dd32.p : D32.p;
+  }
+  // the context at Lh (built on first use and after any change of gauge
+  // field, Mobius parameters or tiling); its solver parameters follow this one's
+  mspcg_ctx* reduced_ctx();
+
+  // partial sums per RHS that the preconditioner writes for the PR dots
+  int64_t precond_partials(Prec O, Prec I) {
+    if (Lh > 0) return transform_blocks(lat.vh, Lh, Ls, O);
+    return (int64_t)nsub * tables(0, I).bps;
   }
 
   // ---------------------------------------------------------------- profiling
@@ -627,6 +685,7 @@ struct mspcg_ctx {
   // dots: partials of <z, r> and <z, r_old> into pz1/pz2 (nsub * bpsC entries).
   int precondition(hipStream_t st, Prec O, Prec I, const FieldPtr& z, const FieldPtr& r, const FieldPtr* rold,
                    int k, double* pz1, double* pz2, const Batch& bt = Batch()) {
+    if (Lh > 0) return precondition_reduced(st, O, I, z, r, rold, k, pz1, pz2, bt);
     const size_t ev = ev_begin(st, 2);
     const int64_t nc = (int64_t)nsub * nC;
     const int nb = bt.n;
@@ -653,12 +712,281 @@ struct mspcg_ctx {
     ev_end(st, ev);
     return k;
   }
+
+  // z = (T^dag Mhat^-1 T + mu) r with Mhat^-1 the same k-step inner CG at Lh;
+  // the PR dots of z with r and r_old fused into the back transform
+  int precondition_reduced(hipStream_t st, Prec O, Prec I, const FieldPtr& z, const FieldPtr& r,
+                           const FieldPtr* rold, int k, double* pz1, double* pz2, const Batch& bt) {
+    const size_t ev = ev_begin(st, 2);
+    mspcg_ctx* c = reduced_ctx();
+    c->sp = sp;
+    const int nb = bt.n;
+    FieldPtr rh = c->field("red.r", O, lat.vh, nb), zh = c->field("red.z", O, lat.vh, nb);
+    const int64_t nzc = c->precond_partials(O, I);
+    double* q1 = c->partial("red.z1", nzc * nb);
+    double* q2 = c->partial("red.z2", nzc * nb);
+    transform(st, O, rh, r, Tdev(O, false), Ls, Lh, lat.vh, 0.0, nullptr, nullptr, nullptr, nullptr, bt);
+    c->precondition(st, O, I, zh, rh, nullptr, k, q1, q2, bt);
+    transform(st, O, z, zh, Tdev(O, true), Lh, Ls, lat.vh, mu_red, &r, rold, pz1, pz2, bt);
+    ev_end(st, ev);
+    return k;
+  }
+
+  // out = (+)_s A_s in: every subdomain's part through its local operator
+  // (storage P), the results put back in place
+  void local_op(hipStream_t st, Prec O, Prec P, const FieldPtr& fo, const FieldPtr& fi) {
+    const SubTables tc = tables(0, P);
+    const int64_t nz = (int64_t)nsub * tc.bps;
+    double* p1 = partial("ap.z1", nz);
+    double* p2 = partial("ap.z2", nz);
+    const int64_t nc = (int64_t)nsub * nC;
+    FieldPtr rs = field("in.r", P, nc), ps = field("in.p", P, nc), t0 = field("in.t0", P, nc), qs = field("in.q", P, nc);
+    sub_restrict(st, O, P, fi, rs, ps, t0, mat(P, MAT_MPHI), lat, tc, nsub, Ls, p1);
+    Asub(st, P, qs, ps, t0, nullptr);
+    sub_prolong(st, O, P, fo, qs, fi, nullptr, lat, tc, nsub, Ls, p1, p2);
+  }
 };
 
 // ==========================================================================
 // solver
 // ==========================================================================
 namespace {
+
+void check_status(mspcg_status s) {
+  if (s != MSPCG_OK) throw Error(s, g_last_error);
+}
+
+}  // namespace
+
+mspcg_ctx* mspcg_ctx::reduced_ctx() {
+  if (red && !red_dirty) return red.get();
+  if (!have_gauge) throw Error(MSPCG_ERR_NO_GAUGE, "no gauge field loaded");
+  if (!have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "the reduced-Ls preconditioner needs mspcg_set_subdomains");
+  if (red && hip_ready) HIPCHK(hipStreamSynchronize(stream));
+  std::unique_ptr<mspcg_ctx> c(new mspcg_ctx(dims, device));
+  check_status(mspcg_share_gauge(c.get(), this));
+  check_status(mspcg_set_mobius(c.get(), Lh, bh, ch, M5, mf));
+  check_status(mspcg_set_subdomains(c.get(), sub));
+  c->sp = sp;
+  red = std::move(c);
+  red_dirty = false;
+  return red.get();
+}
+
+namespace {
+
+// chi^2 = sum_i |M (T^dag Mhat^-1 T + mu) v_i - v_i|^2, M = (+)_s A_s, over nvec
+// device FP64 fields; with grad set, d chi^2/d Re T + i d chi^2/d Im T with
+// Mhat^-1 taken as linear: 2 sum_i [ G(b_i, m_i) + G(a_i, v_i) ], b = Mhat^-1 T v,
+// m = M e, a = Mhat^-1 T m, G(f, g) = sum over sites and colour of f conj(g).
+double reduced_loss_impl(mspcg_ctx* h, int nvec, const double* v, std::vector<double>* grad, hipStream_t st) {
+  const Prec O = to_prec(h->sp.outer_prec), I = to_prec(h->sp.inner_prec);
+  mspcg_ctx* c = h->reduced_ctx();
+  c->sp = h->sp;
+  const int64_t vh = h->lat.vh, nreal = h->n5() * 24;
+  const int Ls = h->Ls, Lh = h->Lh, k = h->sp.inner_iters;
+  FieldPtr vf = h->field("tr.v", O, vh), zf = h->field("tr.z", O, vh), ef = h->field("tr.e", O, vh),
+           mfield = h->field("tr.m", O, vh);
+  FieldPtr rh = c->field("tr.rh", O, vh), bfield = c->field("tr.bh", O, vh), afield = c->field("tr.ah", O, vh);
+  const int64_t nzc = c->precond_partials(O, I);
+  double* q1 = c->partial("tr.q1", nzc);
+  double* q2 = c->partial("tr.q2", nzc);
+  const int nbn = 240;
+  double* pn = h->partial("tr.norm", nbn);
+  const int nent = Lh * 4 * Ls * 4;
+  double2* G = nullptr;
+  double2* part = nullptr;
+  if (grad) {
+    G = h->buf("tr.G", (size_t)nent * sizeof(double2)).as<double2>();
+    part = h->buf("tr.Gpart", (size_t)outer_sum_parts(vh) * nent * sizeof(double2)).as<double2>();
+    zero_batched(st, G, (int64_t)nent * sizeof(double2), Batch());
+  }
+  std::vector<double> hp(nbn);
+  double total = 0;
+  for (int i = 0; i < nvec; ++i) {
+    pack_field(st, vf, v + (int64_t)i * nreal, vh, Ls);
+    transform(st, O, rh, vf, h->Tdev(O, false), Ls, Lh, vh, 0.0, nullptr, nullptr, nullptr, nullptr);
+    c->precondition(st, O, I, bfield, rh, nullptr, k, q1, q2);
+    transform(st, O, zf, bfield, h->Tdev(O, true), Lh, Ls, vh, h->mu_red, &vf, nullptr, nullptr, nullptr);
+    h->local_op(st, O, I, ef, zf);
+    diff_norm(st, O, ef.data, ef.data, vf.data, nreal, pn, nbn);
+    HIPCHK(hipMemcpyAsync(h->h_bounce, pn, nbn * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(hp.data(), h->h_bounce, nbn * sizeof(double));
+    for (int j = 0; j < nbn; ++j) total += hp[j];
+    if (grad) {
+      h->local_op(st, O, I, mfield, ef);
+      transform(st, O, rh, mfield, h->Tdev(O, false), Ls, Lh, vh, 0.0, nullptr, nullptr, nullptr, nullptr);
+      c->precondition(st, O, I, afield, rh, nullptr, k, q1, q2);
+      outer_sum(st, O, bfield, mfield, Lh, Ls, vh, part, G);
+      outer_sum(st, O, afield, vf, Lh, Ls, vh, part, G);
+    }
+  }
+  if (grad) {
+    grad->assign(2 * (size_t)nent, 0.0);
+    HIPCHK(hipMemcpyAsync(h->h_bounce, G, (size_t)nent * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(grad->data(), h->h_bounce, (size_t)nent * sizeof(double2));
+    for (double& g : *grad) g *= 2.0;
+  }
+  return total;
+}
+
+// coefficients c_0..c_4 of chi^2(T + eta d) with Mhat^-1 taken as linear:
+// per vector, Ha = Mhat^-1 T v, Hb = Mhat^-1 d v, e(eta) = e0 + eta e1 + eta^2 e2
+// with e0 = M (T^dag Ha + mu v) - v, e1 = M (T^dag Hb + d^dag Ha), e2 = M d^dag Hb
+void line_quartic_impl(mspcg_ctx* h, int nvec, const double* v, const std::vector<double>& d, double* cf,
+                       hipStream_t st) {
+  const Prec O = to_prec(h->sp.outer_prec), I = to_prec(h->sp.inner_prec);
+  mspcg_ctx* c = h->reduced_ctx();
+  c->sp = h->sp;
+  h->upload_matrix(d, h->D64, h->D32, h->Dd64, h->Dd32);
+  const int64_t vh = h->lat.vh, nreal = h->n5() * 24;
+  const int Ls = h->Ls, Lh = h->Lh, k = h->sp.inner_iters;
+  FieldPtr vf = h->field("tr.v", O, vh), z0 = h->field("tr.z", O, vh), z1 = h->field("tr.m", O, vh),
+           e0 = h->field("tr.e", O, vh), e1 = h->field("tr.e1", O, vh), e2 = h->field("tr.e2", O, vh);
+  FieldPtr rh = c->field("tr.rh", O, vh), ha = c->field("tr.bh", O, vh), hb = c->field("tr.ah", O, vh);
+  const int64_t nzc = c->precond_partials(O, I);
+  double* q1 = c->partial("tr.q1", nzc);
+  double* q2 = c->partial("tr.q2", nzc);
+  const int64_t nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4));
+  double* pa = h->partial("tr.da", nbl);
+  double* pb = h->partial("tr.db", nbl);
+  double* pn = h->partial("tr.norm", 240);
+  std::vector<double> ha_(nbl), hb_(nbl);
+  auto sums = [&](double& x, double& y) {
+    HIPCHK(hipMemcpyAsync(h->h_bounce, pa, nbl * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->h_bounce + nbl * sizeof(double), pb, nbl * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(ha_.data(), h->h_bounce, nbl * sizeof(double));
+    std::memcpy(hb_.data(), h->h_bounce + nbl * sizeof(double), nbl * sizeof(double));
+    x = y = 0;
+    for (int64_t j = 0; j < nbl; ++j) {
+      x += ha_[j];
+      y += hb_[j];
+    }
+  };
+  for (int j = 0; j < 5; ++j) cf[j] = 0;
+  for (int i = 0; i < nvec; ++i) {
+    pack_field(st, vf, v + (int64_t)i * nreal, vh, Ls);
+    transform(st, O, rh, vf, h->Tdev(O, false), Ls, Lh, vh, 0.0, nullptr, nullptr, nullptr, nullptr);
+    c->precondition(st, O, I, ha, rh, nullptr, k, q1, q2);
+    transform(st, O, rh, vf, h->Ddev(O, false), Ls, Lh, vh, 0.0, nullptr, nullptr, nullptr, nullptr);
+    c->precondition(st, O, I, hb, rh, nullptr, k, q1, q2);
+    transform(st, O, z0, ha, h->Tdev(O, true), Lh, Ls, vh, h->mu_red, &vf, nullptr, nullptr, nullptr);
+    h->local_op(st, O, I, e0, z0);
+    diff_norm(st, O, e0.data, e0.data, vf.data, nreal, pn, 240);
+    transform(st, O, z1, hb, h->Tdev(O, true), Lh, Ls, vh, 0.0, nullptr, nullptr, nullptr, nullptr);
+    transform(st, O, z0, ha, h->Ddev(O, true), Lh, Ls, vh, 1.0, &z1, nullptr, nullptr, nullptr);
+    h->local_op(st, O, I, e1, z0);
+    transform(st, O, z1, hb, h->Ddev(O, true), Lh, Ls, vh, 0.0, nullptr, nullptr, nullptr, nullptr);
+    h->local_op(st, O, I, e2, z1);
+    double n00, n01, n02, n11, n12, n22, unused;
+    dot2(st, O, e0.data, e0.data, e1.data, nreal, pa, pb, nbl);
+    sums(n00, n01);
+    dot2(st, O, e2.data, e0.data, e1.data, nreal, pa, pb, nbl);
+    sums(n02, n12);
+    dot2(st, O, e1.data, e1.data, e2.data, nreal, pa, pb, nbl);
+    sums(n11, unused);
+    dot2(st, O, e2.data, e2.data, nullptr, nreal, pa, nullptr, nbl);
+    HIPCHK(hipMemcpyAsync(h->h_bounce, pa, nbl * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(ha_.data(), h->h_bounce, nbl * sizeof(double));
+    n22 = 0;
+    for (int64_t j = 0; j < nbl; ++j) n22 += ha_[j];
+    cf[0] += n00;
+    cf[1] += 2 * n01;
+    cf[2] += n11 + 2 * n02;
+    cf[3] += 2 * n12;
+    cf[4] += n22;
+  }
+}
+
+// minimiser over eta >= 0 of sum c_j eta^j: the best of 0 and the positive
+// real roots of the derivative (a cubic: bracketed between the roots of its
+// derivative and a bound on its roots, then bisected)
+double quartic_min(const double* cf) {
+  auto p = [&](double u) { return (((cf[4] * u + cf[3]) * u + cf[2]) * u + cf[1]) * u + cf[0]; };
+  auto dp = [&](double u) { return ((4 * cf[4] * u + 3 * cf[3]) * u + 2 * cf[2]) * u + cf[1]; };
+  const double d3 = 4 * cf[4], d2 = 3 * cf[3], d1 = 2 * cf[2], d0 = cf[1];
+  // Cauchy bound on the roots of p' (1 + max |lower coefficient / leading|)
+  double bound = 1;
+  if (d3 != 0) bound = 1 + std::max({std::fabs(d2 / d3), std::fabs(d1 / d3), std::fabs(d0 / d3)});
+  else if (d2 != 0) bound = 1 + std::max(std::fabs(d1 / d2), std::fabs(d0 / d2));
+  else if (d1 != 0) bound = 1 + std::fabs(d0 / d1);
+  std::vector<double> pts = {0.0, bound};
+  const double a = 3 * d3, b = 2 * d2, cc = d1;   // derivative of p'
+  if (a != 0) {
+    const double disc = b * b - 4 * a * cc;
+    if (disc >= 0) {
+      const double sq = std::sqrt(disc);
+      for (double r : {(-b - sq) / (2 * a), (-b + sq) / (2 * a)})
+        if (r > 0 && r < bound) pts.push_back(r);
+    }
+  } else if (b != 0) {
+    const double r = -cc / b;
+    if (r > 0 && r < bound) pts.push_back(r);
+  }
+  std::sort(pts.begin(), pts.end());
+  double best = 0, bestv = p(0);
+  for (size_t j = 0; j + 1 < pts.size(); ++j) {
+    double lo = pts[j], hi = pts[j + 1];
+    double flo = dp(lo);
+    const double fhi = dp(hi);
+    if (!(flo == 0 || fhi == 0 || (flo < 0) != (fhi < 0))) continue;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, hi); ++it) {
+      const double mid = 0.5 * (lo + hi);
+      const double fm = dp(mid);
+      if ((fm < 0) == (flo < 0)) {
+        lo = mid;
+        flo = fm;
+      } else {
+        hi = mid;
+      }
+    }
+    const double u = 0.5 * (lo + hi);
+    if (p(u) < bestv) {
+      bestv = p(u);
+      best = u;
+    }
+  }
+  return best;
+}
+
+void set_transform(mspcg_ctx* h, const std::vector<double>& T) {
+  h->Tm = T;
+  h->upload_transform();
+}
+
+// line search along d = -grad + momentum d_prev (Sec. 3.3; readings as the oracle's)
+void train_reduced_impl(mspcg_ctx* h, int nvec, const double* v, int iters, double momentum, double* hist,
+                        hipStream_t st) {
+  std::vector<double> T = h->Tm, g, d_prev(T.size(), 0.0), d(T.size());
+  const double f0 = reduced_loss_impl(h, nvec, v, nullptr, st);
+  if (hist) hist[0] = f0;
+  double last = f0;
+  for (int it = 0; it < iters; ++it) {
+    reduced_loss_impl(h, nvec, v, &g, st);
+    bool any = false;
+    for (size_t i = 0; i < T.size(); ++i) {
+      d[i] = -g[i] + momentum * d_prev[i];
+      any = any || d[i] != 0;
+    }
+    if (!any) {
+      for (int j = it + 1; j <= iters; ++j)
+        if (hist) hist[j] = last;
+      break;
+    }
+    double cf[5];
+    line_quartic_impl(h, nvec, v, d, cf, st);
+    const double eta = quartic_min(cf);
+    for (size_t i = 0; i < T.size(); ++i) T[i] += eta * d[i];
+    set_transform(h, T);
+    d_prev = d;
+    last = reduced_loss_impl(h, nvec, v, nullptr, st);
+    if (hist) hist[it + 1] = last;
+  }
+}
 
 void read_scalars(mspcg_ctx* h, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(h->h_scal, h->scal(), SLOT_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -693,7 +1021,7 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
   int64_t nz = 0;
   double *p_z1 = nullptr, *p_z2 = nullptr;
   if (pre) {
-    nz = (int64_t)h->nsub * h->tables(0, I).bps;
+    nz = h->precond_partials(O, I);
     p_z1 = h->partial("z1", nz);
     p_z2 = h->partial("z2", nz);
   } else {
@@ -965,7 +1293,7 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
   const int64_t bps_hop = full_blocks(vh, Ls, O);
   double* p_pap = h->partial("pap", bps_hop * n);
   int64_t nz = nbl;
-  if (pre) nz = (int64_t)h->nsub * h->tables(0, I).bps;
+  if (pre) nz = h->precond_partials(O, I);
   double* p_z1 = h->partial("z1", nz * n);
   double* p_z2 = h->partial("z2", nz * n);
 
@@ -1331,19 +1659,13 @@ void apply_impl(mspcg_ctx* h, int op, Prec P, const double* in_dev, double* out_
     const Prec O = (P == Prec::F64) ? Prec::F64 : Prec::F32;
     FieldPtr fi = h->field("ap.in", O, vh), fo = h->field("ap.out", O, vh);
     pack_field(st, fi, in_dev, vh, Ls);
-    const SubTables tc = h->tables(0, P);
-    const int64_t nz = (int64_t)h->nsub * tc.bps;
-    double* p1 = h->partial("ap.z1", nz);
-    double* p2 = h->partial("ap.z2", nz);
     if (op == MSPCG_OP_PRECOND) {
+      const int64_t nz = h->precond_partials(O, P);
+      double* p1 = h->partial("ap.z1", nz);
+      double* p2 = h->partial("ap.z2", nz);
       h->precondition(st, O, P, fo, fi, nullptr, h->sp.inner_iters, p1, p2);
     } else {
-      const int64_t nc = (int64_t)h->nsub * h->nC;
-      FieldPtr rs = h->field("in.r", P, nc), ps = h->field("in.p", P, nc), t0 = h->field("in.t0", P, nc),
-               qs = h->field("in.q", P, nc);
-      sub_restrict(st, O, P, fi, rs, ps, t0, h->mat(P, MAT_MPHI), h->lat, tc, h->nsub, Ls, p1);
-      h->Asub(st, P, qs, ps, t0, nullptr);
-      sub_prolong(st, O, P, fo, qs, fi, nullptr, h->lat, tc, h->nsub, Ls, p1, p2);
+      h->local_op(st, O, P, fo, fi);
     }
     unpack_field(st, out_dev, fo, vh, Ls);
     return;
@@ -1432,6 +1754,7 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
     pack_gauge(st, g->g64.p, true, stage.as<double>(), h->lat);
     pack_gauge(st, g->g32.p, false, stage.as<double>(), h->lat);
     h->gs = g;
+    h->red_dirty = true;
     HIPCHK(hipStreamSynchronize(st));
     h->have_gauge = true;
     return MSPCG_OK;
@@ -1454,6 +1777,10 @@ mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double 
     h->upload(h->mats32.p, m32.data(), m32.size() * sizeof(float), h->stream);
     h->tuned.clear();
     h->tuned_us.clear();
+    if (Ls != h->Ls) {   // T has the old shape
+      h->Lh = 0;
+      h->red.reset();
+    }
     h->Ls = Ls;
     h->b = b;
     h->c = c;
@@ -1590,7 +1917,79 @@ mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src) {
     if (h->device != src->device) throw Error(MSPCG_ERR_INVALID_ARG, "handles are on different devices");
     h->ensure_hip();
     h->gs = src->gs;
+    h->red_dirty = true;
     h->have_gauge = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_set_reduced(mspcg_t h, int32_t Lhat, double b_hat, double c_hat, double mu, const double* T) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (Lhat == 0) {
+      if (h->hip_ready) HIPCHK(hipStreamSynchronize(h->stream));
+      h->Lh = 0;
+      h->red.reset();
+      return MSPCG_OK;
+    }
+    if (!h->have_params) throw Error(MSPCG_ERR_NO_PARAMS, "Mobius parameters not set");
+    if (Lhat < 1 || Lhat > h->Ls) throw Error(MSPCG_ERR_INVALID_ARG, "Lhat must be in [1, Ls]");
+    if (!T) throw Error(MSPCG_ERR_INVALID_ARG, "null transform");
+    if (!std::isfinite(b_hat) || !std::isfinite(c_hat) || !std::isfinite(mu))
+      throw Error(MSPCG_ERR_INVALID_ARG, "non-finite parameter");
+    const size_t n = 2 * (size_t)Lhat * 4 * h->Ls * 4;
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(T[i])) throw Error(MSPCG_ERR_INVALID_ARG, "non-finite transform entry");
+    // the reduced operator must be invertible: b (4 - M5) + 1 != 0 (checked by set_mobius on the context)
+    h->ensure_hip();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->Lh = Lhat;
+    h->bh = b_hat;
+    h->ch = c_hat;
+    h->mu_red = mu;
+    h->Tm.assign(T, T + n);
+    h->upload_transform();
+    h->red.reset();
+    h->red_dirty = true;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_get_reduced(mspcg_t h, int32_t* Lhat, double* T) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !Lhat) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    *Lhat = h->Lh;
+    if (T && h->Lh > 0) std::memcpy(T, h->Tm.data(), h->Tm.size() * sizeof(double));
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_reduced_loss(mspcg_t h, int32_t nvec, const double* v, double* chi2, double* grad) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !v || !chi2) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (nvec < 1) throw Error(MSPCG_ERR_INVALID_ARG, "nvec must be >= 1");
+    need_state(h);
+    if (h->Lh == 0) throw Error(MSPCG_ERR_INVALID_ARG, "no reduced-Ls preconditioner set");
+    if (!h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "needs mspcg_set_subdomains");
+    h->ensure_hip();
+    std::vector<double> g;
+    *chi2 = reduced_loss_impl(h, nvec, v, grad ? &g : nullptr, h->stream);
+    if (grad) std::memcpy(grad, g.data(), g.size() * sizeof(double));
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32_t iters, double momentum,
+                                 double* history) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !v) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (nvec < 1 || iters < 0) throw Error(MSPCG_ERR_INVALID_ARG, "nvec must be >= 1 and iters >= 0");
+    if (!std::isfinite(momentum)) throw Error(MSPCG_ERR_INVALID_ARG, "non-finite momentum");
+    need_state(h);
+    if (h->Lh == 0) throw Error(MSPCG_ERR_INVALID_ARG, "no reduced-Ls preconditioner set");
+    if (!h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "needs mspcg_set_subdomains");
+    h->ensure_hip();
+    train_reduced_impl(h, nvec, v, iters, momentum, history, h->stream);
     return MSPCG_OK;
   });
 }

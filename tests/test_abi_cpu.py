@@ -151,3 +151,24 @@ def test_server_lifecycle_and_validation_without_device_work():
     finally:
         assert M.mspcg_server_destroy(s) == M.MSPCG_OK
     assert M.mspcg_server_destroy(None) == M.MSPCG_OK
+
+
+def test_reduced_ls_entry_points_validate_before_the_device():
+    import paper_2104_05615_amd as M
+    h = ctypes.c_void_p()
+    assert M.mspcg_create(ctypes.byref(h), (ctypes.c_int32 * 4)(8, 8, 8, 8), 0) == M.MSPCG_OK
+    try:
+        T = (ctypes.c_double * (2 * 4 * 4 * 8 * 4))()
+        # no Mobius parameters yet
+        assert M.mspcg_set_reduced(h, 4, 1.5, 0.5, 0.1, T) == M.MSPCG_ERR_NO_PARAMS
+        assert M.mspcg_set_reduced(h, 0, 0.0, 0.0, 0.0, None) == M.MSPCG_OK     # switching off is always fine
+        L = ctypes.c_int32(7)
+        assert M.mspcg_get_reduced(h, ctypes.byref(L), None) == M.MSPCG_OK and L.value == 0
+        c = ctypes.c_double()
+        buf = (ctypes.c_double * 16)()
+        assert M.mspcg_reduced_loss(h, 1, buf, ctypes.byref(c), None) == M.MSPCG_ERR_NO_GAUGE
+        assert M.mspcg_reduced_loss(h, 0, buf, ctypes.byref(c), None) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_train_reduced(h, 1, buf, -1, 0.5, None) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_train_reduced(h, 1, buf, 2, float("nan"), None) == M.MSPCG_ERR_INVALID_ARG
+    finally:
+        M.mspcg_destroy(h)

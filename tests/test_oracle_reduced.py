@@ -10,7 +10,8 @@ gradient, the quartic line search and the training loop.
 * the gradient matches central finite differences of chi^2 for a linear
   Hermitian Mhat^-1, in every real and imaginary direction sampled (fails a
   dropped term, a missing factor 2 or conjugate);
-* the quartic line search returns the exact minimiser of a quartic;
+* the line quartic equals chi^2 along the line for a linear Mhat^-1, and its
+  minimiser is exact;
 * training with a linear Mhat^-1 never increases chi^2 and lowers it.
 """
 import numpy as np
@@ -108,10 +109,25 @@ def test_gradient_matches_finite_differences():
             assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (idx, unit, fd, an)
 
 
-def test_quartic_line_search_is_exact_on_a_quartic():
-    f = lambda e: 3.0 * (e - 1.7) ** 2 * ((e - 1.7) ** 2 + 0.5) + 2.0
-    eta, val, _ = oracle.quartic_line_min(f, 0.3)
-    assert abs(eta - 1.7) < 1e-8 and abs(val - 2.0) < 1e-10
+def test_line_quartic_is_chi2_along_the_line_for_a_linear_inverse():
+    op, oph, til = ops(4, 2)
+    H = dense_local_inverse(oph, til)
+    T = 0.3 * rand((2, 4, 4, 4))
+    d = rand((2, 4, 4, 4))
+    vs = [rand((4, op.vh, 4, 3)) for _ in range(2)]
+    c = oracle.line_quartic(op, oph, til, T, d, 0.1, vs, 0, inverse=H)
+    for eta in (0.0, 0.37, -1.3, 2.0):
+        direct = oracle.chi2(op, oph, til, T + eta * d, 0.1, vs, 0, inverse=H)
+        assert abs(np.polyval(c[::-1], eta) - direct) < 1e-10 * direct
+
+
+def test_quartic_min_is_exact():
+    # 3 (e - 1.7)^2 ((e - 1.7)^2 + 0.5) + 2, expanded
+    p = np.polynomial.polynomial.Polynomial([-1.7, 1.0])
+    q = 3 * p ** 2 * (p ** 2 + 0.5) + 2
+    assert abs(oracle.quartic_min(q.coef) - 1.7) < 1e-9
+    # the minimum over eta >= 0 of an increasing quartic is at 0
+    assert oracle.quartic_min([1.0, 2.0, 1.0, 0.0, 1.0]) == 0.0
 
 
 def test_training_lowers_the_loss():
@@ -122,5 +138,6 @@ def test_training_lowers_the_loss():
     for s in range(2):
         T0[s, :, 2 * s, :] = np.eye(4)
     T, hist = oracle.train_transform(op, oph, til, T0, 0.1, vs, 0, iters=4, inverse=H)
+    assert hist[-1] < 0.5 * hist[0]
     assert all(b <= a * (1 + 1e-12) for a, b in zip(hist, hist[1:]))
     assert hist[-1] < 0.9 * hist[0]
