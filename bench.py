@@ -53,9 +53,10 @@ def stage_bytes(cfg, inner_prec):
     """Algorithmic bytes of one launch of each hop stage: every input site
     read once, every output written once, the epilogue's second field (w) and,
     in the last hop, the field of the fused <p, A p> partial read once where
-    they are nonzero, and the FP32 links the launch needs read once each: the
-    8 links of each output 4D site (shared over Ls), at most every link of the
-    lattice (subdomain regions overlap their neighbours, so the links of one
+    they are nonzero, and the links the launch needs read once each (FP32 for
+    the outer hops, FP16 for the subdomain hops of the 16- and 8-bit formats):
+    the 8 links of each output 4D site (shared over Ls), at most every link of
+    the lattice (subdomain regions overlap their neighbours, so the links of one
     launch of a subdomain hop repeat across subdomains).  Keys: profiling
     kinds of the library (21..24 outer FP32 hops of A, 11..14 subdomain hops
     h1..h4)."""
@@ -64,15 +65,17 @@ def stage_bytes(cfg, inner_prec):
     Ls = cfg.Ls
     sp32 = 96
     sp16 = {"int8": 28, "fp16": 52, "bf16": 52, "fp32": 96, "fp64": 192}[inner_prec]
-    link = 8 * 18 * 4
+    link = 8 * 18 * 4                    # the 8 FP32 links of an output 4D site
+    # subdomain hops of the 16- and 8-bit formats read FP16 links
+    link_in = 8 * 18 * {"int8": 2, "fp16": 2, "bf16": 2, "fp32": 4, "fp64": 8}[inner_prec]
     n5 = vh * Ls
     out = {21: 2 * sp32 * n5 + link * vh, 22: 3 * sp32 * n5 + link * vh,
            23: 2 * sp32 * n5 + link * vh, 24: 4 * sp32 * n5 + link * vh}
     nC, nN1, nN2 = region_counts(cfg.sub, cfg.dims)
     ns = cfg.n_subdomains
-    all_links = 2 * vh * 4 * 18 * 4
+    all_links = 2 * vh * 4 * link_in // 8
     for k, (sin, sout) in {11: (nC, nN1), 12: (nN1 + nC, nN2), 13: (nN2, nN1), 14: (nN1 + 2 * nC, nC)}.items():
-        out[k] = ns * Ls * sp16 * (sin + sout) + min(ns * link * sout, all_links)
+        out[k] = ns * Ls * sp16 * (sin + sout) + min(ns * link_in * sout, all_links)
     return out, (nC, nN1, nN2)
 
 
@@ -321,20 +324,27 @@ def reduced_bench(args):
         T0[j, :, 2 * j, :] = np.eye(4)
     out = {"metric": "reduced-Ls MSPCG time-to-solution @ rel resid 1e-10", "unit": "s", "config": cfg.name,
            "full": {"Ls": cfg.Ls, "time_s": t_full, "outer_iters": st_full.outer_iters}, "reduced": []}
-    for mu in args.mu:
-        s.set_reduced(Lh, mu=mu, T=T0)
+    # Mobius parameters of the reduced operator: those of the full one, and
+    # the same b - c with b + c scaled by Ls / Lhat (the Mobius scale that keeps
+    # b + c times the number of slices)
+    bc = [(cfg.b, cfg.c)]
+    if args.alpha_match:
+        a = (cfg.b + cfg.c) * cfg.Ls / Lh
+        bc.append(((a + cfg.b - cfg.c) / 2, (a - cfg.b + cfg.c) / 2))
+    for (bh, ch), mu in [(x, m) for x in bc for m in args.mu]:
+        s.set_reduced(Lh, bh, ch, mu=mu, T=T0)
         s.set_solver(**params)
         t = time.perf_counter()
         hist = s.train_reduced(len(vs), V.data_ptr(), args.train_iters, momentum=0.5)
         t_train = time.perf_counter() - t
         log(f"[reduced] mu={mu}: trained in {t_train:.1f}s, chi2 {hist[0]:.3e} -> {hist[-1]:.3e}")
         t_red, st_red = solve(maxiter=5000)
-        s.set_reduced(Lh, mu=mu, T=T0)
+        s.set_reduced(Lh, bh, ch, mu=mu, T=T0)
         t_dec, st_dec = solve(maxiter=5000)
-        log(f"[reduced] Lhat={Lh} mu={mu}: chi2 {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f}s; solve "
+        log(f"[reduced] Lhat={Lh} b_hat={bh:g} c_hat={ch:g} mu={mu}: chi2 {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f}s; solve "
             f"{t_red:.3f}s, {st_red.outer_iters} iters (status {st_red.status}); untrained T: {t_dec:.3f}s, "
             f"{st_dec.outer_iters} iters")
-        out["reduced"].append({"Lhat": Lh, "mu": mu, "train_s": t_train, "chi2_first": hist[0], "chi2_last": hist[-1],
+        out["reduced"].append({"Lhat": Lh, "b_hat": bh, "c_hat": ch, "mu": mu, "train_s": t_train, "chi2_first": hist[0], "chi2_last": hist[-1],
                                "time_s": t_red, "outer_iters": st_red.outer_iters, "status": st_red.status,
                                "true_rel_resid": st_red.true_rel_resid,
                                "untrained": {"time_s": t_dec, "outer_iters": st_dec.outer_iters}})
@@ -425,6 +435,8 @@ def main():
     ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve", "kernels", "reduced"])
     ap.add_argument("--mu", type=float, nargs="+", default=[0.05, 0.2], help="mu values of the reduced-Ls scan")
     ap.add_argument("--train-iters", type=int, default=10, help="training steps of the reduced-Ls transform")
+    ap.add_argument("--alpha-match", action="store_true",
+                    help="also scan the reduced operator with b + c scaled by Ls / Lhat")
     ap.add_argument("--log-every", type=int, default=0, help="solver progress line every N outer iterations")
     ap.add_argument("--no-cg64", action="store_true", help="skip the FP64 CG baseline")
     ap.add_argument("--no-prec-compare", action="store_true",

@@ -309,7 +309,8 @@ __device__ __forceinline__ T load_site_unscaled(const Field<S>& f, uint32_t i, T
 // 16-byte loads:  U[parity][mu][vh][10] of complex L2.
 // --------------------------------------------------------------------------
 template <typename L> struct Gauge {
-  using c2 = typename std::conditional<sizeof(L) == 8, double2, float2>::type;
+  using c2 = typename std::conditional<
+      sizeof(L) == 8, double2, typename std::conditional<sizeof(L) == 4, float2, __half2>::type>::type;
   const c2* data;
   int64_t vh;
 };
@@ -325,6 +326,19 @@ __device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu,
       const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, off + k * 16, 0, 0);
       u[2 * k] = (T)__hiloint2double(c.y, c.x);
       u[2 * k + 1] = (T)__hiloint2double(c.w, c.z);
+    }
+  } else if constexpr (sizeof(C2) == 4) {
+    // FP16 record (40 bytes): entries 0-3, 4-7 and 8.  The conversions fold
+    // into the consumers' v_fma_mix_f32 (the SU(3) product), so the link
+    // costs no conversion instructions.
+    const u32x4 c0 = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    const u32x4 c1 = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+    const uint32_t c2w = __builtin_amdgcn_raw_buffer_load_b32(r, off + 32, 0, 0);
+    const uint32_t w[9] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2w};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      u[2 * k] = (T)half_lo(w[k]);
+      u[2 * k + 1] = (T)half_hi(w[k]);
     }
   } else {
 #pragma unroll

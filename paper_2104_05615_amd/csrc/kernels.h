@@ -103,9 +103,10 @@ void unpack_field(hipStream_t st, double* canon, const FieldPtr& in, int64_t nsi
                   const Batch& bt = Batch());
 // zero bytes_per_rhs bytes of every masked RHS (bytes_per_rhs % 16 == 0)
 void zero_batched(hipStream_t st, void* data, int64_t bytes_per_rhs, const Batch& bt);
-// gauge: canonical [T][Z][Y][X][4][3][3] complex FP64 -> [parity][mu][vh][10] double2 / float2
+// gauge: canonical [T][Z][Y][X][4][3][3] complex FP64 -> [parity][mu][vh][10] double2 / float2 / half2
+// (bytes_per_real 8, 4 or 2)
 // (9 entries of a link padded to 10)
-void pack_gauge(hipStream_t st, void* out, bool fp64, const double* canon, const Lattice& lat);
+void pack_gauge(hipStream_t st, void* out, int bytes_per_real, const double* canon, const Lattice& lat);
 
 // ---------------------------------------------------------------- outer BLAS-1 (FP64 / FP32 fields)
 int64_t blas_blocks(int64_t nchunks);

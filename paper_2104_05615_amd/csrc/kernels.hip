@@ -131,14 +131,15 @@ static void hop_sub_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, c
                       const Lattice& lat, int out_parity, const SubTables& tb, int nsub, int Ls, bool dagger,
                       const Epilogue& epi, const Batch& bt, const Sched& sc) {
   using T = calc_t<S>;
-  SubGeo<T> g;
+  using L = typename std::conditional<StoreTraits<S>::scaled, __half, T>::type;
+  SubGeo<T, L> g;
   g.tb = tb;
   g.lat = lat;
   g.par = out_parity;
-  g.g.data = reinterpret_cast<const typename Gauge<T>::c2*>(gauge);
+  g.g.data = reinterpret_cast<const typename Gauge<L>::c2*>(gauge);
   g.g.vh = lat.vh;
   const int ns = sites_per_block(Ls, out.prec);
-  launch_hop<SubGeo<T>, S>(st, g, (int64_t)nsub * tb.bps, out, in, w, Ls, ns, dagger, epi, bt, sc);
+  launch_hop<SubGeo<T, L>, S>(st, g, (int64_t)nsub * tb.bps, out, in, w, Ls, ns, dagger, epi, bt, sc);
 }
 
 void hop_sub(hipStream_t st, Prec p, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, const void* gauge,
@@ -371,17 +372,23 @@ __global__ void k_pack_gauge(C2* out, const double* canon, Lattice lat) {
     for (int k = 0; k < 9; ++k) {
       const double* src = canon + ((lex * 4 + mu) * 9 + k) * 2;
       C2 c;
-      c.x = src[0];
-      c.y = src[1];
+      if constexpr (sizeof(C2) == 4) {
+        c.x = __float2half_rn((float)src[0]);
+        c.y = __float2half_rn((float)src[1]);
+      } else {
+        c.x = src[0];
+        c.y = src[1];
+      }
       out[((int64_t)(par * 4 + mu) * lat.vh + cb) * 10 + k] = c;
     }
 }
 
-void pack_gauge(hipStream_t st, void* out, bool fp64, const double* canon, const Lattice& lat) {
+void pack_gauge(hipStream_t st, void* out, int bytes_per_real, const double* canon, const Lattice& lat) {
   const int64_t V = 2 * lat.vh;
   dim3 grid((unsigned)((V + 255) / 256)), block(256);
-  if (fp64) hipLaunchKernelGGL(k_pack_gauge<double2>, grid, block, 0, st, (double2*)out, canon, lat);
-  else hipLaunchKernelGGL(k_pack_gauge<float2>, grid, block, 0, st, (float2*)out, canon, lat);
+  if (bytes_per_real == 8) hipLaunchKernelGGL(k_pack_gauge<double2>, grid, block, 0, st, (double2*)out, canon, lat);
+  else if (bytes_per_real == 4) hipLaunchKernelGGL(k_pack_gauge<float2>, grid, block, 0, st, (float2*)out, canon, lat);
+  else hipLaunchKernelGGL(k_pack_gauge<__half2>, grid, block, 0, st, (__half2*)out, canon, lat);
   LAUNCH_CHECK();
 }
 

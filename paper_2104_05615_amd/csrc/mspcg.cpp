@@ -332,7 +332,7 @@ struct mspcg_ctx {
 
   // device links, FP64 and FP32 layouts; shared between handles on one field
   struct GaugeStore {
-    DevBuf g64, g32;
+    DevBuf g64, g32, g16;
   };
   std::shared_ptr<GaugeStore> gs;
   bool have_gauge = false;
@@ -466,6 +466,8 @@ struct mspcg_ctx {
     return mats32.as<float>() + off;
   }
   const void* gauge(Prec p) const { return p == Prec::F64 ? gs->g64.p : gs->g32.p; }
+  // links of the subdomain hops: FP16 records for the 16- and 8-bit formats
+  const void* gauge_sub(Prec p) const { return scaled(p) ? gs->g16.p : gauge(p); }
 
   // bytes of the workspaces, matrices and tables this handle holds (not the
   // gauge field)
@@ -672,7 +674,7 @@ struct mspcg_ctx {
     auto run = [&](int which, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, int par, bool dag,
                    const Epilogue& E) {
       const size_t ev = ev_begin(st, 10 + which);
-      hop_sub(st, I, out, in, w, gauge(I), lat, par, tables(which, I), nsub, Ls, dag, E, bt, sc);
+      hop_sub(st, I, out, in, w, gauge_sub(I), lat, par, tables(which, I), nsub, Ls, dag, E, bt, sc);
       ev_end(st, ev);
     };
     run(1, a, t0, nullptr, 1, false, epi(I, -1, MAT_Q));
@@ -1751,8 +1753,10 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
     auto g = std::make_shared<mspcg_ctx::GaugeStore>();
     g->g64.ensure((size_t)V * 4 * 10 * sizeof(double2));
     g->g32.ensure((size_t)V * 4 * 10 * sizeof(float2));
-    pack_gauge(st, g->g64.p, true, stage.as<double>(), h->lat);
-    pack_gauge(st, g->g32.p, false, stage.as<double>(), h->lat);
+    g->g16.ensure((size_t)V * 4 * 10 * 2 * sizeof(uint16_t));
+    pack_gauge(st, g->g64.p, 8, stage.as<double>(), h->lat);
+    pack_gauge(st, g->g32.p, 4, stage.as<double>(), h->lat);
+    pack_gauge(st, g->g16.p, 2, stage.as<double>(), h->lat);
     h->gs = g;
     h->red_dirty = true;
     HIPCHK(hipStreamSynchronize(st));

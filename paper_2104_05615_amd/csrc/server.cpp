@@ -291,7 +291,7 @@ mspcg_status mspcg_server_add_field(mspcg_server_t s, const int32_t dims[4], con
     Field f;
     for (int m = 0; m < 4; ++m) f.dims[m] = dims[m];
     const int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
-    f.bytes = V * 4 * 10 * (16 + 8);   // FP64 and FP32 link layouts (9 entries padded to 10)
+    f.bytes = V * 4 * 10 * (16 + 8 + 4);   // FP64, FP32 and FP16 link layouts (9 entries padded to 10)
     std::lock_guard<std::mutex> lk(s->mu);
     while (s->used + f.bytes > s->budget && s->evict_one(nullptr)) {
     }

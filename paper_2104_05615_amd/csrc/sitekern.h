@@ -124,11 +124,14 @@ template <typename T> struct FullGeo {
 // ---------------------------------------------------------------- subdomains
 // (tables: SubTables in common.h)
 
-template <typename T> struct SubGeo {
+// links in precision L: FP32/FP64 with the fields of that precision, FP16
+// with the 16- and 8-bit formats (the paper's half-precision preconditioner
+// stores its links in 16 bits too)
+template <typename T, typename LinkT = T> struct SubGeo {
   SubTables tb;
   Lattice lat;
   int par;        // output parity (global)
-  Gauge<T> g;
+  Gauge<LinkT> g;
 
   __device__ __forceinline__ SiteRef locate(int64_t blk, int sl, int ns, int Ls, int s) const {
     SiteRef r;

@@ -119,7 +119,7 @@ def test_server_admission_by_budget_and_oom():
     h.set_solver(tol=1e-10, inner_iters=4)
     est, _ = h.footprint(2)
     h.close()
-    fields = sum(int(np.prod(v[0])) * 4 * 10 * 24 for v in FIELDS.values())
+    fields = sum(int(np.prod(v[0])) * 4 * 10 * 28 for v in FIELDS.values())
     budget = fields + int(1.3 * est)
     say(f"[gpu] server: budget {budget} B = fields {fields} + 1.3 x {est}")
     res, info = run(4, budget=budget)
