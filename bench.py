@@ -22,6 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+MFMA_F16_PEAK_TFLOPS = 2500.0   # dense FP16 MFMA, MI355X
 HBM_PEAK_GBS = 8000.0
 METRIC = "MSPCG vs CG time-to-solution @ rel resid 1e-10; Dslash GB/s; p50/p99"
 
@@ -563,6 +564,19 @@ def main():
             "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name, dom_key),
             "avg_launch_ms": dom["avg_ms"], "launches": dom["launches"],
             "algorithmic_bytes_per_launch": dom["algorithmic_bytes"]}
+    # MFMA work of the fifth-dimension epilogue: useful dense flops (one real
+    # Ls x Ls matrix per chirality on the 12 reals of that chirality: 48 Ls
+    # flops per 5D site and matrix; the centre-field matrix of h2 only on the
+    # centre region, where that field lives) against the FP16 MFMA peak
+    nC, nN1, nN2 = regions
+    mats = {11: nN1, 12: nN2 + nC, 13: nN1, 14: 2 * nC}
+    mfma = {}
+    for k, n4 in mats.items():
+        if str(k) in kernels:
+            fl = 48 * cfg.Ls * cfg.Ls * n4 * cfg.n_subdomains
+            tf = fl / (kernels[str(k)]["avg_ms"] * 1e-3) / 1e12
+            mfma[str(k)] = {"useful_flops_per_launch": fl, "TFLOPs": tf, "peak_TFLOPs": MFMA_F16_PEAK_TFLOPS,
+                            "frac": tf / MFMA_F16_PEAK_TFLOPS}
     outer_b = sum(sbytes[k] for k in (21, 22, 23, 24)) / 4
     inner_b = sum(sbytes[k] for k in (11, 12, 13, 14)) / 4
     avg_out = ms_out / max(n_out, 1)
@@ -603,6 +617,7 @@ def main():
                    "inner_hop_GBps": gbs_in, "inner_hop_avg_ms": avg_in, "inner_launches": n_in,
                    "outer_hop_ms_total": ms_out, "inner_hop_ms_total": ms_in, "regions_C_N1_N2": regions},
         "roofline": roof,
+        "mfma_epilogue": mfma,
         "p50_p99": None,
     }
     if args.oracle_check:

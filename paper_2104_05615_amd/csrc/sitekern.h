@@ -181,10 +181,33 @@ template <typename T, typename LinkT = T> struct SubGeo {
       }
       return;
     }
+    const uint32_t iF = (base_in + (uint32_t)(hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s;
+    const uint32_t iB = (base_in + (uint32_t)(hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s;
+    if constexpr (std::is_same<S, __half>::value) {
+      // FP16: the stored halves are projected under the guard too, so a rim
+      // site's absent terms cost no arithmetic at all
+      uint4 qF[3], qB[3];
+      T uF[18], uB[18], h[12], gh[12];
+      const T scF = load_site_raw16(in, iF, qF);
+      load_link(g, par, MU, lx >> 1, uF);
+      const T scB = load_site_raw16(in, iB, qB);
+      load_link(g, 1 - par, MU, lb >> 1, uB);
+      if (hf) {
+        project_h<MU, SF>(qF, h);
+        su3_mul_half<false>(uF, h, gh);
+        accumulate<MU, SF, S>(gh, scF, acc);
+      }
+      if (hb) {
+        project_h<MU, SB>(qB, h);
+        su3_mul_half<true>(uB, h, gh);
+        accumulate<MU, SB, S>(gh, scB, acc);
+      }
+      return;
+    }
     T hF[12], hB[12], uF[18], uB[18], gh[12];
-    const T scF = load_project<MU, SF>(in, (base_in + (uint32_t)(hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s, hF);
+    const T scF = load_project<MU, SF>(in, iF, hF);
     load_link(g, par, MU, lx >> 1, uF);
-    const T scB = load_project<MU, SB>(in, (base_in + (uint32_t)(hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s, hB);
+    const T scB = load_project<MU, SB>(in, iB, hB);
     load_link(g, 1 - par, MU, lb >> 1, uB);
     if (hf) {
       su3_mul_half<false>(uF, hF, gh);
