@@ -61,7 +61,7 @@ static void launch_hop_mf(hipStream_t st, const Geo& geo, int64_t nblocks, const
                           const Sched& sc) {
   using T = calc_t<S>;
   const bool tileB = w != nullptr && !epi.w_identity && epi.E0 != nullptr;
-  const size_t lds = site_lds_bytes<T>(ns, Ls, tileB, MF);
+  const size_t lds = site_lds_bytes<T>(ns, Ls, tileB, MF, UsesMfma<S>::half_ops);
   Field<S> wf = w ? typed<S>(*w) : Field<S>{};
   Field<S> df = epi.dotf ? typed<S>(*epi.dotf) : Field<S>{};
   const T* E0 = (const T*)epi.E0;

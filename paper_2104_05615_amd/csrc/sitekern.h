@@ -337,25 +337,39 @@ __device__ __forceinline__ half4_t mfma_a16(const float* E, int chi, int Ls, int
 // t = 4 (lane / 16) + v of site column lane % 16, clamped to Ls - 1 (for the
 // f16 path; the f32 path reads rows 4 kk + lane / 16).  Computed once, so a
 // tile's reads are these pointers plus the component index.
+// (element offsets into the tile: 32-bit, the tile base is uniform)
 struct Rows {
-  const float* p[4];
+  uint32_t o[4];
 };
-__device__ __forceinline__ Rows tile_rows(const float* tile, int stride, int Ls, int lane, bool f16) {
+__device__ __forceinline__ Rows tile_rows(int stride, int Ls, int lane, bool f16) {
   const int col = lane & 15, g = lane >> 4;
   Rows r;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int t = f16 ? 4 * g + v : 4 * v + g;
-    r.p[v] = tile + col * stride + (t < Ls ? t : Ls - 1) * 24;
+    r.o[v] = (uint32_t)(col * stride + (t < Ls ? t : Ls - 1) * 24);
   }
   return r;
 }
 
 // one tile: acc += E_chi H[:, site = lane%16, component q]
-__device__ __forceinline__ float4_t mfma_tile16(half4_t a, const Rows& rows, int q, float ics, float4_t acc) {
+__device__ __forceinline__ float4_t mfma_tile16(half4_t a, const float* tile, const Rows& rows, int q, float ics,
+                                                float4_t acc) {
   half4_t b;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) b[v] = (_Float16)(rows.p[v][q] * ics);
+  for (int v = 0; v < 4; ++v) b[v] = (_Float16)(tile[rows.o[v] + q] * ics);
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+}
+
+// B operand rows of an FP16 tile (the centre field of the FP16-operand
+// epilogue, stored as its values over the largest one of their row)
+// acc += E_chi W[:, site, q] with W(t) = stored(t) x rs[t] (rs = row scale x
+// column ics); rows as tile_rows(.., f16 = true) of the FP16 tile
+__device__ __forceinline__ float4_t mfma_tile16_h(half4_t a, const _Float16* tile, const Rows& rows, int q,
+                                                  const float* rs, float4_t acc) {
+  half4_t b;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) b[v] = (_Float16)((float)tile[rows.o[v] + q] * rs[v]);
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
 }
 
@@ -376,9 +390,11 @@ __device__ __forceinline__ A32 mfma_a32(const float* E, int chi, int Ls, int lan
   return r;
 }
 
-__device__ __forceinline__ float4_t mfma_tile32(const A32& a, const Rows& rows, int q, float4_t acc) {
+__device__ __forceinline__ float4_t mfma_tile32(const A32& a, const float* tile, const Rows& rows, int q,
+                                                float4_t acc) {
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], rows.p[kk][q], acc, 0, 0, 0);
+  for (int kk = 0; kk < 4; ++kk)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], tile[rows.o[kk] + q], acc, 0, 0, 0);
   return acc;
 }
 
@@ -386,19 +402,24 @@ __device__ __forceinline__ float4_t mfma_tile32(const A32& a, const Rows& rows, 
 //   red   [16] doubles            (block reduction scratch)
 //   mats  [2][2][Ls][Ls] of T     (E0, E1; VALU path only)
 //   tileA [ns][tile_stride] of T  (hop result)
-//   tileB [ns][tile_stride] of T  (centre field, when E0 is dense)
+//   tileB [ns][tile_stride] of T  (centre field, when E0 is dense; FP16 in the
+//                                  MFMA path with FP16 operands, each row over
+//                                  its largest value, kept in smaxw)
 //   tileO [ns][tile_stride] of T  (MFMA path with fewer than 3 wavefronts:
 //                                  epilogue result; otherwise tileA is reused)
 //   smax  [ns][Ls] floats         (MFMA path with FP16 operands: column maxima)
+//   smaxw [ns][Ls] floats         (same, with a centre field: row maxima of tileB)
 template <typename T>
-inline size_t site_lds_bytes(int ns, int Ls, bool tileB, bool mfma) {
+inline size_t site_lds_bytes(int ns, int Ls, bool tileB, bool mfma, bool half_ops = false) {
   size_t n = 16 * sizeof(double);
   if (!mfma) n += sizeof(T) * (size_t)(4 * Ls * Ls);
-  n += sizeof(T) * (size_t)((tileB ? 2 : 1) * ns * tile_stride(Ls));
+  n += sizeof(T) * (size_t)(ns * tile_stride(Ls));
+  if (tileB) n += (mfma && half_ops ? 2 : sizeof(T)) * (size_t)(ns * tile_stride(Ls));
   if (mfma) {
     const int nwave = site_block_threads(ns, Ls) / 64;
     if (nwave < 3) n += sizeof(T) * (size_t)(ns * tile_stride(Ls));
     n += sizeof(float) * (size_t)(ns * Ls);
+    if (tileB && half_ops) n += sizeof(float) * (size_t)(ns * Ls);
   }
   return n;
 }
@@ -438,9 +459,14 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   T* mats = reinterpret_cast<T*>(red + 16);
   T* tileA = MF ? mats : mats + 4 * Ls * Ls;
   const bool e0_dense = HASW && !w_identity && E0 != nullptr;
+  constexpr bool HOB = MF && UsesMfma<S>::half_ops;   // FP16 centre-field tile
   T* tileB = tileA + ns * tile_stride(Ls);
-  T* tileO = tileB + (e0_dense ? ns * tile_stride(Ls) : 0);
+  _Float16* tileB16 = reinterpret_cast<_Float16*>(tileB);
+  unsigned char* afterB = reinterpret_cast<unsigned char*>(tileB) +
+                          (e0_dense ? (size_t)(HOB ? 2 : sizeof(T)) * ns * tile_stride(Ls) : 0);
+  T* tileO = reinterpret_cast<T*>(afterB);
   float* smax = reinterpret_cast<float*>(tileO + ((blockDim.x >> 6) < 3 ? ns * tile_stride(Ls) : 0));
+  float* smaxw = smax + ns * Ls;
 
   const int tid = threadIdx.x;
   const bool inb = tid < ns * Ls;
@@ -483,7 +509,20 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
     if (early || hw) load_site(w, hw ? (uint32_t)r.w5 : 0u, wv);
 #pragma unroll
     for (int k = 0; k < 24; ++k) wv[k] = hw ? wv[k] : (T)0;
-    if (e0_dense && inb) tile_put(myB, s, wv);
+    if (e0_dense && inb) {
+      if constexpr (HOB) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf((float)wv[k]));
+        const float im = m > 0.f ? 1.f / m : 0.f;
+        _Float16* d = tileB16 + sl * tile_stride(Ls) + s * 24;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) d[k] = (_Float16)((float)wv[k] * im);
+        smaxw[sl * Ls + s] = m;
+      } else {
+        tile_put(myB, s, wv);
+      }
+    }
   }
   T pv[24];
   if (early && dot_partial) load_site(dotf, valid ? (uint32_t)r.out5 : 0u, pv);
@@ -527,16 +566,22 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
           if (e0_live) f0[chi] = mfma_a32((const float*)E0, chi, Ls, lane);
         }
       }
-      const Rows rA = tile_rows((const float*)tileA, tile_stride(Ls), Ls, lane, HO);
-      const Rows rB = tile_rows((const float*)tileB, tile_stride(Ls), Ls, lane, HO);
-      auto tile = [&](int chi, int q, const Rows& ra, const Rows& rb) {
+      // tileA and tileB share the row layout: one set of row offsets
+      const Rows rA = tile_rows(tile_stride(Ls), Ls, lane, HO);
+      float rsw[4];   // centre-field rows: row maximum x column ics
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int t = 4 * g + v;
+        rsw[v] = (HOB && e0_live) ? smaxw[col * Ls + (t < Ls ? t : Ls - 1)] * ics : 0.f;
+      }
+      auto tile = [&](int chi, int q, const Rows& ra) {
         float4_t acc = {0.f, 0.f, 0.f, 0.f};
         if (HO) {
-          if (E1) acc = mfma_tile16(a1[chi], ra, q, ics, acc);
-          if (e0_live) acc = mfma_tile16(a0[chi], rb, q, ics, acc);
+          if (E1) acc = mfma_tile16(a1[chi], (const float*)tileA, ra, q, ics, acc);
+          if (e0_live) acc = mfma_tile16_h(a0[chi], tileB16, ra, q, rsw, acc);
         } else {
-          if (E1) acc = mfma_tile32(f1[chi], ra, q, acc);
-          if (e0_live) acc = mfma_tile32(f0[chi], rb, q, acc);
+          if (E1) acc = mfma_tile32(f1[chi], (const float*)tileA, ra, q, acc);
+          if (e0_live) acc = mfma_tile32(f0[chi], (const float*)tileB, ra, q, acc);
         }
         return acc;
       };
@@ -556,15 +601,12 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
         constexpr int NW = decltype(nwc)::value;
         constexpr int NJ = 24 / NW;
         const int w = __builtin_amdgcn_readfirstlane(wave);
-        Rows ra = rA, rb = rB;
+        Rows ra = rA;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          ra.p[v] += w;
-          rb.p[v] += w;
-        }
+        for (int v = 0; v < 4; ++v) ra.o[v] += (uint32_t)w;
         float4_t accs[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) accs[j] = tile(j * NW >= 12 ? 1 : 0, j * NW, ra, rb);
+        for (int j = 0; j < NJ; ++j) accs[j] = tile(j * NW >= 12 ? 1 : 0, j * NW, ra);
         __syncthreads();
         T* ob = tileA + col * tile_stride(Ls) + w;
 #pragma unroll
@@ -586,7 +628,7 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int q = wave + j * nwave;
-          if (q < 24) accs[j] = tile(q / 12, q, rA, rB);
+          if (q < 24) accs[j] = tile(q / 12, q, rA);
         }
         __syncthreads();
 #pragma unroll
@@ -595,7 +637,7 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
           if (q < 24) put(tileA, q, accs[j]);
         }
       } else {
-        for (int q = wave; q < 24; q += nwave) put(tileO, q, tile(q / 12, q, rA, rB));
+        for (int q = wave; q < 24; q += nwave) put(tileO, q, tile(q / 12, q, rA));
         dst = tileO;
       }
       __syncthreads();
