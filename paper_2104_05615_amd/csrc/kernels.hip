@@ -132,13 +132,26 @@ static void hop_sub_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, c
                       const Epilogue& epi, const Batch& bt, const Sched& sc) {
   using T = calc_t<S>;
   using L = typename std::conditional<StoreTraits<S>::scaled, __half, T>::type;
+  constexpr bool half = std::is_same<S, __half>::value;
+  const int ns = sites_per_block(Ls, out.prec);
+  // FP16 with Ls a multiple of 4: SU(3) products on 4 x 4 x 4 MFMA blocks
+  // (each block's four lanes are four slices of one 4D site)
+  if (half && Ls % 4 == 0) {
+    SubGeo<T, L, half> g;
+    g.tb = tb;
+    g.lat = lat;
+    g.par = out_parity;
+    g.g.data = reinterpret_cast<const typename Gauge<L>::c2*>(gauge);
+    g.g.vh = lat.vh;
+    launch_hop<SubGeo<T, L, half>, S>(st, g, (int64_t)nsub * tb.bps, out, in, w, Ls, ns, dagger, epi, bt, sc);
+    return;
+  }
   SubGeo<T, L> g;
   g.tb = tb;
   g.lat = lat;
   g.par = out_parity;
   g.g.data = reinterpret_cast<const typename Gauge<L>::c2*>(gauge);
   g.g.vh = lat.vh;
-  const int ns = sites_per_block(Ls, out.prec);
   launch_hop<SubGeo<T, L>, S>(st, g, (int64_t)nsub * tb.bps, out, in, w, Ls, ns, dagger, epi, bt, sc);
 }
 

@@ -16,6 +16,9 @@ namespace mspcg {
 
 template <typename S> using calc_t = typename StoreTraits<S>::calc;
 
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
 // Register fence between the directions of a hop: the 24 accumulators are
 // final here and no later memory access moves above this point.  Without it
 // the compiler overlaps all eight neighbour terms and needs every register.
@@ -121,13 +124,135 @@ template <typename T> struct FullGeo {
   }
 };
 
+// ---------------------------------------------------------------- FP16 hop terms on MFMA
+//
+// The SU(3) products of a 16-bit hop run on v_mfma_f32_4x4x4f16: 16
+// independent 4 x 4 x 4 blocks per wavefront, block b on lanes 4b .. 4b + 3;
+// lane 4b + i holds row i of the block's A (4 K entries) and column i of its
+// B (4 K entries), and receives column i of the product (4 rows).  With Ls a
+// multiple of 4 and s fastest, the 4 lanes of a block are 4 fifth-dimension
+// slices of one 4D site, so they share the link of every term and the guard
+// of every term.
+//
+// Per spin of the projected half spinor (Sec. 2.2) a term is
+//     g = U (psi_a + f psi_b),   f = +-1 or +-i,
+// taken as a real 8 x 12 by 12 x 4 product per block: K runs over the real
+// and imaginary parts of the three colours of psi_a and of f psi_b (the
+// projection happens in the FP32 accumulation, so nothing is rounded to 16
+// bits on the way), the rows are the real parts (first product) and the
+// imaginary parts (second product) of the three output colours, and the
+// columns are the block's 4 lanes.  Lane i supplies the rows of colour
+// min(i, 2) (row 3 duplicates row 2 and its output is unused) and its own
+// stored halves as B.  Multiplying a stored half pair by f only moves and
+// negates halves, which is exact.
+
+__device__ __forceinline__ half4_t hpair(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(half4_t, (u32x2){lo, hi});
+}
+
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return __builtin_amdgcn_alignbit(w, w, 16); }
+
+// a (re, im) half pair times f: F = 1, -1, 2 (+i) or -2 (-i)
+template <int F> __device__ __forceinline__ uint32_t cmul_word(uint32_t w) {
+  if constexpr (F == 1) return w;
+  else if constexpr (F == -1) return w ^ 0x80008000u;
+  else if constexpr (F == 2) return swap_halves(w) ^ 0x00008000u;   // (-im, re)
+  else return swap_halves(w) ^ 0x80000000u;                         // (im, -re)
+}
+
+// The three stored words a lane needs of an FP16 link record: row `a` of U
+// (DAG false) or column `a` (DAG true, for U^dag), one (re, im) half pair per
+// entry.
+template <bool DAG>
+__device__ __forceinline__ u32x4 link_words(const Gauge<__half>& g, int parity, int mu, uint32_t site, int a) {
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(g.data, (uint64_t)80 * (uint64_t)g.vh * 4u);
+  const uint32_t off = ((uint32_t)(parity * 4 + mu) * (uint32_t)g.vh + site) * 40u;
+  u32x4 w;
+  w.x = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (uint32_t)(DAG ? a : 3 * a), 0, 0);
+  w.y = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (uint32_t)(DAG ? 3 + a : 3 * a + 1), 0, 0);
+  w.z = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (uint32_t)(DAG ? 6 + a : 3 * a + 2), 0, 0);
+  w.w = 0;
+  return w;
+}
+
+// the 24 stored halves of a site as three 16-byte chunks, and its scale
+__device__ __forceinline__ float load_site_v16(const Field<__half>& f, uint32_t i, u32x4& c0, u32x4& c1,
+                                               u32x4& c2) {
+  using C = typename Field<__half>::chunk;
+  const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+  const uint32_t off = i * (uint32_t)sizeof(C);
+  const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+  c0 = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  c1 = __builtin_amdgcn_raw_buffer_load_b128(r, off + cs, 0, 0);
+  c2 = __builtin_amdgcn_raw_buffer_load_b128(r, off + 2 * cs, 0, 0);
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
+}
+
+// Those words as the A rows of the real-part (re: out.re = sum_b re_b . psi_b)
+// and imaginary-part (im) outputs of colour a, one (re, im)-ordered pair per
+// input colour b.
+template <bool DAG>
+__device__ __forceinline__ void link_rows(u32x4 lw, uint32_t* re, uint32_t* im) {
+  const uint32_t w[3] = {lw.x, lw.y, lw.z};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if constexpr (!DAG) {             // U_ab:        (Re, -Im) and (Im, Re)
+      re[b] = w[b] ^ 0x80000000u;
+      im[b] = swap_halves(w[b]);
+    } else {                          // conj(U_ba):  (Re, Im) and (-Im, Re)
+      re[b] = w[b];
+      im[b] = swap_halves(w[b]) ^ 0x00008000u;
+    }
+  }
+}
+
+// g (6 FP32: colour-major re, im) = U (u + F d) for one spin
+template <int F>
+__device__ __forceinline__ void spin_mfma(const uint32_t* u, const uint32_t* d, const uint32_t* xr,
+                                          const uint32_t* xi, float* g) {
+  const half4_t b0 = hpair(u[0], u[1]);
+  const half4_t b1 = hpair(cmul_word<F>(d[0]), cmul_word<F>(d[1]));
+  const half4_t b2 = hpair(u[2], cmul_word<F>(d[2]));
+  const float4_t z = {0.f, 0.f, 0.f, 0.f};
+  float4_t re = __builtin_amdgcn_mfma_f32_4x4x4f16(hpair(xr[0], xr[1]), b0, z, 0, 0, 0);
+  float4_t im = __builtin_amdgcn_mfma_f32_4x4x4f16(hpair(xi[0], xi[1]), b0, z, 0, 0, 0);
+  re = __builtin_amdgcn_mfma_f32_4x4x4f16(hpair(xr[0], xr[1]), b1, re, 0, 0, 0);
+  im = __builtin_amdgcn_mfma_f32_4x4x4f16(hpair(xi[0], xi[1]), b1, im, 0, 0, 0);
+  re = __builtin_amdgcn_mfma_f32_4x4x4f16(hpair(xr[2], xr[2]), b2, re, 0, 0, 0);
+  im = __builtin_amdgcn_mfma_f32_4x4x4f16(hpair(xi[2], xi[2]), b2, im, 0, 0, 0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    g[2 * c] = re[c];
+    g[2 * c + 1] = im[c];
+  }
+}
+
+// one hop term: acc += sc [ g ; SIGN G^dag g ], g = U h, h = (1 + SIGN gamma_mu) psi
+// (the projection factors are those of project_h)
+template <int MU, int SIGN, bool DAG>
+__device__ __forceinline__ void term_mfma(u32x4 q0, u32x4 q1, u32x4 q2, u32x4 lw, float sc, float* acc) {
+  uint32_t xr[3], xi[3];
+  link_rows<DAG>(lw, xr, xi);
+  const uint32_t w[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+  float gh[12];
+  // spin 0 pairs with spin 3 (mu = x, y) or 2 (z, t); spin 1 with the other
+  constexpr int D0 = MU < 2 ? 9 : 6, D1 = MU < 2 ? 6 : 9;
+  constexpr int F0 = MU == 0 ? -2 * SIGN : MU == 1 ? -SIGN : MU == 2 ? -2 * SIGN : SIGN;
+  constexpr int F1 = MU == 0 ? -2 * SIGN : MU == 1 ? SIGN : MU == 2 ? 2 * SIGN : SIGN;
+  spin_mfma<F0>(w + 0, w + D0, xr, xi, gh);
+  spin_mfma<F1>(w + 3, w + D1, xr, xi, gh + 6);
+  reconstruct_fma<MU, SIGN>(gh, sc, acc);
+}
+
 // ---------------------------------------------------------------- subdomains
 // (tables: SubTables in common.h)
 
 // links in precision L: FP32/FP64 with the fields of that precision, FP16
 // with the 16- and 8-bit formats (the paper's half-precision preconditioner
-// stores its links in 16 bits too)
-template <typename T, typename LinkT = T> struct SubGeo {
+// stores its links in 16 bits too).  MW: FP16 fields with Ls a multiple of 4,
+// whose SU(3) products run on MFMA blocks (term_mfma).
+template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
   SubTables tb;
   Lattice lat;
   int par;        // output parity (global)
@@ -219,6 +344,40 @@ template <typename T, typename LinkT = T> struct SubGeo {
     }
   }
 
+  // MFMA-term path: one direction's two terms as loaded (stored halves, the
+  // lane's link words, scales, presence)
+  struct Terms {
+    u32x4 f0, f1, f2, b0, b1, b2;   // stored halves of the two neighbours
+    u32x4 uF, uB;                   // the lane's link words (3 used)
+    float scF, scB;
+    bool hf, hb;
+  };
+
+  template <int MU>
+  __device__ __forceinline__ void load_terms(const Field<__half>& in, uint32_t base_in, const int* gco, uint32_t lx,
+                                             const int* nb, int s, int Ls, int a, Terms& t) const {
+    const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
+    t.hf = jf >= 0;
+    t.hb = jb >= 0;
+    const int L = lat.ext(MU);
+    const uint32_t st = lat.stride(MU);
+    const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
+    const uint32_t iF = (base_in + (uint32_t)(t.hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s;
+    const uint32_t iB = (base_in + (uint32_t)(t.hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s;
+    t.scF = load_site_v16(in, iF, t.f0, t.f1, t.f2);
+    t.uF = link_words<false>(g, par, MU, lx >> 1, a);
+    t.scB = load_site_v16(in, iB, t.b0, t.b1, t.b2);
+    t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a);
+  }
+
+  template <int MU, bool DAG>
+  __device__ __forceinline__ void apply_terms(const Terms& t, float* acc) const {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    if (t.hf) term_mfma<MU, SF, false>(t.f0, t.f1, t.f2, t.uF, t.scF, acc);
+    if (t.hb) term_mfma<MU, SB, true>(t.b0, t.b1, t.b2, t.uB, t.scB, acc);
+  }
+
   template <bool DAG, typename S>
   __device__ __forceinline__ void hop(const Field<S>& in, const SiteRef& r, int s, int Ls, T* acc) const {
 #pragma unroll
@@ -239,6 +398,26 @@ template <typename T, typename LinkT = T> struct SubGeo {
     const int4 n1 = reinterpret_cast<const int4*>(tb.nbr)[2 * r.site + 1];
     const int nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
     const uint32_t base_in = (uint32_t)r.d * (uint32_t)tb.n_in;
+    if constexpr (MW) {
+      static_assert(std::is_same<S, __half>::value && std::is_same<LinkT, __half>::value, "MFMA hop terms: FP16 only");
+      // SU(3) products on MFMA blocks of 4 fifth-dimension slices, two
+      // directions in flight: the loads of direction mu + 2 are issued
+      // before the arithmetic of direction mu + 1
+      const int a = min((int)(threadIdx.x & 3u), 2);
+      Terms t0, t1;
+      load_terms<0>(in, base_in, gco, lx, nb, s, Ls, a, t0);
+      load_terms<1>(in, base_in, gco, lx, nb, s, Ls, a, t1);
+      apply_terms<0, DAG>(t0, acc);
+      pin(acc);
+      load_terms<2>(in, base_in, gco, lx, nb, s, Ls, a, t0);
+      apply_terms<1, DAG>(t1, acc);
+      pin(acc);
+      load_terms<3>(in, base_in, gco, lx, nb, s, Ls, a, t1);
+      apply_terms<2, DAG>(t0, acc);
+      pin(acc);
+      apply_terms<3, DAG>(t1, acc);
+      return;
+    }
     dir<0, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
     pin(acc);
     dir<1, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
@@ -303,9 +482,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // FP16, every column (site) scaled into [-1, 1] by its largest entry) or of
 // four v_mfma_f32_16x16x4_f32 (FP32).  Lane l of a wavefront holds column
 // l % 16 and the fifth-dimension rows 4 (l / 16) .. 4 (l / 16) + 3.
-
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
 
 template <typename S> struct UsesMfma {
   static constexpr bool value = !std::is_same<S, double>::value;
@@ -449,8 +625,14 @@ struct HopWork {
   }
 };
 
+// minimum wavefronts per SIMD the register allocation aims for
+template <typename Geo, typename S, bool HASW> constexpr int hop_waves() { return sizeof(calc_t<S>) == 8 ? 2 : 4; }
+
+template <typename G> struct IsSubGeo : std::false_type {};
+template <typename T, typename L, bool M> struct IsSubGeo<SubGeo<T, L, M>> : std::true_type {};
+
 template <typename Geo, typename S, bool DAG, bool HASW, bool MF>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(calc_t<S>) == 8 ? 2 : 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hop_waves<Geo, S, HASW>())))
 k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int Ls, int ns, const calc_t<S>* E0,
       const calc_t<S>* E1, int w_identity, double* dot_partial, HopWork wk) {
   using T = calc_t<S>;
@@ -497,16 +679,21 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   T* myA = tileA + sl * tile_stride(Ls);
   T* myB = tileB + sl * tile_stride(Ls);
   if (inb) tile_put(myA, s, h);
-  // centre field and the fused dot's field: read without a branch (index 0
-  // where there is nothing to read, then zeros selected), so that their loads
-  // are in flight with the last direction of the hop and with the epilogue.
-  // FP64 keeps the branch: it has no registers to spare for the overlap.
+  // centre field and the fused dot's field: on the full lattice read without
+  // a branch (index 0 where there is nothing to read, then zeros selected),
+  // so that their loads are in flight with the last direction of the hop and
+  // with the epilogue.  FP64 keeps the branch: it has no registers to spare
+  // for the overlap.  A subdomain hop's centre field covers the centre region
+  // only, a small part of the output region: there a branch-free read would
+  // send most lanes of the launch to one address, so only the lanes with a
+  // centre site read.
   constexpr bool early = sizeof(T) == 4;
+  constexpr bool early_w = early && !IsSubGeo<Geo>::value;
   T wv[24];
   bool hw = false;
   if (HASW) {
     hw = valid && r.w5 >= 0;
-    if (early || hw) load_site(w, hw ? (uint32_t)r.w5 : 0u, wv);
+    if (early_w || hw) load_site(w, hw ? (uint32_t)r.w5 : 0u, wv);
 #pragma unroll
     for (int k = 0; k < 24; ++k) wv[k] = hw ? wv[k] : (T)0;
     if (e0_dense && inb) {

@@ -153,6 +153,7 @@ SUBS = [
     ((8, 8, 4, 2), 6, (4, 4, 4, 2)),
     ((12, 4, 2, 2), 3, (4, 4, 2, 2)),
     ((8, 8, 8, 8), 8, (4, 4, 4, 4)),
+    ((8, 4, 4, 8), 12, (4, 4, 4, 4)),   # the benchmark's Ls: 16-bit terms on 4 x 4 x 4 MFMA blocks
 ]
 
 
