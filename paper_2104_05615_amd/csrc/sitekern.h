@@ -576,7 +576,7 @@ __device__ __forceinline__ float4_t mfma_tile32(const A32& a, const float* tile,
 
 // LDS layout of the site kernels:
 //   red   [16] doubles            (block reduction scratch)
-//   mats  [2][2][Ls][Ls] of T     (E0, E1; VALU path only)
+//   mats  [2][2][Ls][Ls] of T     (E0, E1)
 //   tileA [ns][tile_stride] of T  (hop result)
 //   tileB [ns][tile_stride] of T  (centre field, when E0 is dense; FP16 in the
 //                                  MFMA path with FP16 operands, each row over
@@ -588,7 +588,7 @@ __device__ __forceinline__ float4_t mfma_tile32(const A32& a, const float* tile,
 template <typename T>
 inline size_t site_lds_bytes(int ns, int Ls, bool tileB, bool mfma, bool half_ops = false) {
   size_t n = 16 * sizeof(double);
-  if (!mfma) n += sizeof(T) * (size_t)(4 * Ls * Ls);
+  n += sizeof(T) * (size_t)(4 * Ls * Ls);
   n += sizeof(T) * (size_t)(ns * tile_stride(Ls));
   if (tileB) n += (mfma && half_ops ? 2 : sizeof(T)) * (size_t)(ns * tile_stride(Ls));
   if (mfma) {
@@ -639,7 +639,7 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* red = reinterpret_cast<double*>(lds_raw);
   T* mats = reinterpret_cast<T*>(red + 16);
-  T* tileA = MF ? mats : mats + 4 * Ls * Ls;
+  T* tileA = mats + 4 * Ls * Ls;
   const bool e0_dense = HASW && !w_identity && E0 != nullptr;
   constexpr bool HOB = MF && UsesMfma<S>::half_ops;   // FP16 centre-field tile
   T* tileB = tileA + ns * tile_stride(Ls);
@@ -654,11 +654,24 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   const bool inb = tid < ns * Ls;
   const int sl = inb ? tid / Ls : 0, s = inb ? tid - sl * Ls : 0;
 
+  const int nm = 2 * Ls * Ls;
   if constexpr (!MF) {
-    const int nm = 2 * Ls * Ls;
     for (int k = tid; k < nm; k += blockDim.x) {
       if (E0) mats[k] = E0[k];
       if (E1) mats[nm + k] = E1[k];
+    }
+  }
+  // MFMA path (Ls <= 16, at least 16 Ls threads: at most two entries of each
+  // matrix per thread): the matrices are read here, in flight with the hop's
+  // loads, and written to LDS after the hop, where the epilogue reads its
+  // operands with LDS latency.
+  T epre[4];
+  if constexpr (MF) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = min(tid + j * (int)blockDim.x, nm - 1);
+      epre[j] = e0_dense ? E0[k] : (T)0;
+      epre[2 + j] = E1 ? E1[k] : (T)0;
     }
   }
 
@@ -679,6 +692,16 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   T* myA = tileA + sl * tile_stride(Ls);
   T* myB = tileB + sl * tile_stride(Ls);
   if (inb) tile_put(myA, s, h);
+  if constexpr (MF) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = tid + j * (int)blockDim.x;
+      if (k < nm) {
+        if (e0_dense) mats[k] = epre[j];
+        if (E1) mats[nm + k] = epre[2 + j];
+      }
+    }
+  }
   // centre field and the fused dot's field: on the full lattice read without
   // a branch (index 0 where there is nothing to read, then zeros selected),
   // so that their loads are in flight with the last direction of the hop and
@@ -746,11 +769,11 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
 #pragma unroll
       for (int chi = 0; chi < 2; ++chi) {
         if (HO) {
-          if (E1) a1[chi] = mfma_a16((const float*)E1, chi, Ls, lane);
-          if (e0_live) a0[chi] = mfma_a16((const float*)E0, chi, Ls, lane);
+          if (E1) a1[chi] = mfma_a16((const float*)mats + nm, chi, Ls, lane);
+          if (e0_live) a0[chi] = mfma_a16((const float*)mats, chi, Ls, lane);
         } else {
-          if (E1) f1[chi] = mfma_a32((const float*)E1, chi, Ls, lane);
-          if (e0_live) f0[chi] = mfma_a32((const float*)E0, chi, Ls, lane);
+          if (E1) f1[chi] = mfma_a32((const float*)mats + nm, chi, Ls, lane);
+          if (e0_live) f0[chi] = mfma_a32((const float*)mats, chi, Ls, lane);
         }
       }
       // tileA and tileB share the row layout: one set of row offsets
