@@ -132,10 +132,10 @@ static void hop_sub_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, c
                       const Epilogue& epi, const Batch& bt, const Sched& sc) {
   using T = calc_t<S>;
   using L = typename std::conditional<StoreTraits<S>::scaled, __half, T>::type;
-  constexpr bool half = std::is_same<S, __half>::value;
+  constexpr bool half = std::is_same<S, __half>::value || std::is_same<S, int8_t>::value;
   const int ns = sites_per_block(Ls, out.prec);
-  // FP16 with Ls a multiple of 4: SU(3) products on 4 x 4 x 4 MFMA blocks
-  // (each block's four lanes are four slices of one 4D site)
+  // FP16 and 8-bit storage with Ls a multiple of 4: SU(3) products on 4 x 4 x 4
+  // MFMA blocks (each block's four lanes are four slices of one 4D site)
   if (half && Ls % 4 == 0) {
     SubGeo<T, L, half> g;
     g.tb = tb;

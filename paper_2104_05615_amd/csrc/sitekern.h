@@ -189,6 +189,40 @@ __device__ __forceinline__ float load_site_v16(const Field<__half>& f, uint32_t 
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
 }
 
+// the 24 stored int8 values of a site as three 8-byte chunks, and its scale
+__device__ __forceinline__ float load_site_v8(const Field<int8_t>& f, uint32_t i, u32x2& c0, u32x2& c1, u32x2& c2) {
+  using C = typename Field<int8_t>::chunk;
+  const __amdgpu_buffer_rsrc_t r = field_rsrc(f);
+  const uint32_t off = i * (uint32_t)sizeof(C);
+  const uint32_t cs = (uint32_t)f.stride * (uint32_t)sizeof(C);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.scale, (uint64_t)f.stride * 4u);
+  c0 = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  c1 = __builtin_amdgcn_raw_buffer_load_b64(r, off + cs, 0, 0);
+  c2 = __builtin_amdgcn_raw_buffer_load_b64(r, off + 2 * cs, 0, 0);
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, i * 4u, 0, 0));
+}
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// Eight int8 values (two words, component order) as four FP16 (re, im)
+// pairs, exactly: each byte, biased to u = q + 128 in [0, 255], becomes the
+// low mantissa bits of the FP16 number 1024 + u (exponent byte 0x64), and one
+// packed FP16 subtraction of 1152 leaves q (integers below 2048 are exact).
+__device__ __forceinline__ u32x4 i8_to_h16(u32x2 c) {
+  const uint32_t x0 = c.x ^ 0x80808080u, x1 = c.y ^ 0x80808080u;
+  const uint32_t e = 0x64646464u;
+  // v_perm_b32 result bytes: (u_lo, 0x64, u_hi, 0x64) for bytes 0,1 and 2,3
+  const uint32_t w[4] = {__builtin_amdgcn_perm(e, x0, 0x04010400u), __builtin_amdgcn_perm(e, x0, 0x04030402u),
+                         __builtin_amdgcn_perm(e, x1, 0x04010400u), __builtin_amdgcn_perm(e, x1, 0x04030402u)};
+  const half2_t off = {(_Float16)1152.0f, (_Float16)1152.0f};
+  u32x4 r;
+  r.x = __builtin_bit_cast(uint32_t, __builtin_bit_cast(half2_t, w[0]) - off);
+  r.y = __builtin_bit_cast(uint32_t, __builtin_bit_cast(half2_t, w[1]) - off);
+  r.z = __builtin_bit_cast(uint32_t, __builtin_bit_cast(half2_t, w[2]) - off);
+  r.w = __builtin_bit_cast(uint32_t, __builtin_bit_cast(half2_t, w[3]) - off);
+  return r;
+}
+
 // Those words as the A rows of the real-part (re: out.re = sum_b re_b . psi_b)
 // and imaginary-part (im) outputs of colour a, one (re, im)-ordered pair per
 // input colour b.
@@ -251,7 +285,8 @@ __device__ __forceinline__ void term_mfma(u32x4 q0, u32x4 q1, u32x4 q2, u32x4 lw
 // links in precision L: FP32/FP64 with the fields of that precision, FP16
 // with the 16- and 8-bit formats (the paper's half-precision preconditioner
 // stores its links in 16 bits too).  MW: FP16 fields with Ls a multiple of 4,
-// whose SU(3) products run on MFMA blocks (term_mfma).
+// whose SU(3) products run on MFMA blocks (term_mfma; the 8-bit format's
+// integers are FP16 operands exactly).
 template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
   SubTables tb;
   Lattice lat;
@@ -348,13 +383,14 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
   // lane's link words, scales, presence)
   struct Terms {
     u32x4 f0, f1, f2, b0, b1, b2;   // stored halves of the two neighbours
+    u32x2 g0, g1, g2, k0, k1, k2;   // (8-bit format) stored bytes of the two neighbours
     u32x4 uF, uB;                   // the lane's link words (3 used)
     float scF, scB;
     bool hf, hb;
   };
 
-  template <int MU>
-  __device__ __forceinline__ void load_terms(const Field<__half>& in, uint32_t base_in, const int* gco, uint32_t lx,
+  template <int MU, typename S>
+  __device__ __forceinline__ void load_terms(const Field<S>& in, uint32_t base_in, const int* gco, uint32_t lx,
                                              const int* nb, int s, int Ls, int a, Terms& t) const {
     const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
     t.hf = jf >= 0;
@@ -364,18 +400,30 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
     const uint32_t lb = (gco[MU] == 0) ? lx + (uint32_t)(L - 1) * st : lx - st;
     const uint32_t iF = (base_in + (uint32_t)(t.hf ? jf : 0)) * (uint32_t)Ls + (uint32_t)s;
     const uint32_t iB = (base_in + (uint32_t)(t.hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s;
-    t.scF = load_site_v16(in, iF, t.f0, t.f1, t.f2);
-    t.uF = link_words<false>(g, par, MU, lx >> 1, a);
-    t.scB = load_site_v16(in, iB, t.b0, t.b1, t.b2);
-    t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a);
+    if constexpr (std::is_same<S, int8_t>::value) {
+      t.scF = load_site_v8(in, iF, t.g0, t.g1, t.g2);
+      t.uF = link_words<false>(g, par, MU, lx >> 1, a);
+      t.scB = load_site_v8(in, iB, t.k0, t.k1, t.k2);
+      t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a);
+    } else {
+      t.scF = load_site_v16(in, iF, t.f0, t.f1, t.f2);
+      t.uF = link_words<false>(g, par, MU, lx >> 1, a);
+      t.scB = load_site_v16(in, iB, t.b0, t.b1, t.b2);
+      t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a);
+    }
   }
 
-  template <int MU, bool DAG>
+  template <int MU, bool DAG, typename S>
   __device__ __forceinline__ void apply_terms(const Terms& t, float* acc) const {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
-    if (t.hf) term_mfma<MU, SF, false>(t.f0, t.f1, t.f2, t.uF, t.scF, acc);
-    if (t.hb) term_mfma<MU, SB, true>(t.b0, t.b1, t.b2, t.uB, t.scB, acc);
+    if constexpr (std::is_same<S, int8_t>::value) {
+      if (t.hf) term_mfma<MU, SF, false>(i8_to_h16(t.g0), i8_to_h16(t.g1), i8_to_h16(t.g2), t.uF, t.scF, acc);
+      if (t.hb) term_mfma<MU, SB, true>(i8_to_h16(t.k0), i8_to_h16(t.k1), i8_to_h16(t.k2), t.uB, t.scB, acc);
+    } else {
+      if (t.hf) term_mfma<MU, SF, false>(t.f0, t.f1, t.f2, t.uF, t.scF, acc);
+      if (t.hb) term_mfma<MU, SB, true>(t.b0, t.b1, t.b2, t.uB, t.scB, acc);
+    }
   }
 
   template <bool DAG, typename S>
@@ -399,7 +447,8 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
     const int nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
     const uint32_t base_in = (uint32_t)r.d * (uint32_t)tb.n_in;
     if constexpr (MW) {
-      static_assert(std::is_same<S, __half>::value && std::is_same<LinkT, __half>::value, "MFMA hop terms: FP16 only");
+      static_assert((std::is_same<S, __half>::value || std::is_same<S, int8_t>::value) &&
+                        std::is_same<LinkT, __half>::value, "MFMA hop terms: FP16 and 8-bit formats");
       // SU(3) products on MFMA blocks of 4 fifth-dimension slices, two
       // directions in flight: the loads of direction mu + 2 are issued
       // before the arithmetic of direction mu + 1
@@ -407,15 +456,15 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
       Terms t0, t1;
       load_terms<0>(in, base_in, gco, lx, nb, s, Ls, a, t0);
       load_terms<1>(in, base_in, gco, lx, nb, s, Ls, a, t1);
-      apply_terms<0, DAG>(t0, acc);
+      apply_terms<0, DAG, S>(t0, acc);
       pin(acc);
       load_terms<2>(in, base_in, gco, lx, nb, s, Ls, a, t0);
-      apply_terms<1, DAG>(t1, acc);
+      apply_terms<1, DAG, S>(t1, acc);
       pin(acc);
       load_terms<3>(in, base_in, gco, lx, nb, s, Ls, a, t1);
-      apply_terms<2, DAG>(t0, acc);
+      apply_terms<2, DAG, S>(t0, acc);
       pin(acc);
-      apply_terms<3, DAG>(t1, acc);
+      apply_terms<3, DAG, S>(t1, acc);
       return;
     }
     dir<0, DAG>(in, base_in, gco, lx, nb, s, Ls, acc);
