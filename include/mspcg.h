@@ -190,7 +190,11 @@ mspcg_status mspcg_solve_batch_device(mspcg_t h, int32_t nrhs, const double* b, 
  * hop launch runs one workgroup per (site block, RHS); the candidates are
  * the RHS order (RHS outermost, or the RHS of one site block adjacent so that
  * they read its links from one L2) and the XCD mapping (contiguous site-block
- * ranges per XCD, or the hardware's round robin).  Kinds: 0 = full-lattice
+ * ranges per XCD, or the hardware's round robin) and, for the full-lattice
+ * hops, the order of the site blocks: lexicographic, or time slices swept
+ * chunk by chunk (a chunk of a few z-planes and rows, run through every t
+ * before the next, so that the +-t neighbour spinors of the blocks in flight
+ * are still in the XCD's L2), four chunk sizes.  Kinds: 0 = full-lattice
  * hops in the outer precision, 1 = FP64 hops, 2 = subdomain hops (needs a
  * tiling).  No schedule changes a result: partial sums are indexed by
  * (RHS, site block), not by workgroup.  The choice is kept in the handle
@@ -203,6 +207,19 @@ mspcg_status mspcg_autotune(mspcg_t h, int32_t nrhs);
  * the tuned time of the kind's four hops in microseconds (0 when untuned).
  * Errors: INVALID_ARG for NULL or an unknown kind. */
 mspcg_status mspcg_get_schedule(mspcg_t h, int32_t kind, int32_t nrhs, int32_t* order, int32_t* xcd, double* us);
+
+/* Pin the schedule of (kind, nrhs) (extension: lets a caller reuse a tuned
+ * schedule or compare schedules): order and xcd as above, tchunk = 0 for the
+ * lexicographic block order of the full-lattice hops or 1..4 for the chunked
+ * sweep with chunks of about (80 << tchunk) KB of input spinors (falls back
+ * to lexicographic when site blocks do not tile whole z-planes; ignored by
+ * kind 2).  Results do not depend on it.  Kept until set_mobius /
+ * set_subdomains.  mspcg_get_tchunk returns the block order in use (untuned:
+ * 3 for the full-lattice kinds, 0 for kind 2).
+ * Errors: INVALID_ARG (unknown kind, nrhs outside [1, 1024], order, xcd or
+ * tchunk out of range, NULL). */
+mspcg_status mspcg_set_schedule(mspcg_t h, int32_t kind, int32_t nrhs, int32_t order, int32_t xcd, int32_t tchunk);
+mspcg_status mspcg_get_tchunk(mspcg_t h, int32_t kind, int32_t nrhs, int32_t* tchunk);
 
 /* Apply one operator (mspcg_op) in precision `prec` to a host FP64 field and
  * return the result as host FP64: the input is converted to the storage of

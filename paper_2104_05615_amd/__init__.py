@@ -116,6 +116,8 @@ _SIGS = {
     "mspcg_server_wait": [_h, ctypes.c_int64, ctypes.POINTER(mspcg_stats), ctypes.POINTER(_d)],
     "mspcg_server_info": [_h, ctypes.POINTER(mspcg_server_stats)],
     "mspcg_get_schedule": [_h, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_d)],
+    "mspcg_set_schedule": [_h, _i32, _i32, _i32, _i32, _i32],
+    "mspcg_get_tchunk": [_h, _i32, _i32, ctypes.POINTER(_i32)],
     "mspcg_apply": [_h, _i32, ctypes.c_int, _p, _p],
     "mspcg_apply_device": [_h, _i32, ctypes.c_int, _p, _p, _p],
     "mspcg_set_profiling": [_h, _i32],
@@ -331,6 +333,15 @@ class MSPCG:
         o, x, us = _i32(), _i32(), _d()
         _check(mspcg_get_schedule(self._h, int(kind), int(nrhs), ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)))
         return o.value, x.value, us.value
+
+    def set_schedule(self, kind, nrhs=1, order=0, xcd=1, tchunk=0):
+        _check(mspcg_set_schedule(self._h, int(kind), int(nrhs), int(order), int(xcd), int(tchunk)))
+
+    def tchunk(self, kind, nrhs=1):
+        """Block order of the full-lattice hops of a kind: 0 lexicographic, k > 0 chunked t sweep."""
+        t = _i32()
+        _check(mspcg_get_tchunk(self._h, int(kind), int(nrhs), ctypes.byref(t)))
+        return t.value
 
     def apply(self, op, prec, psi):
         a = _host_f64(psi, self._n())

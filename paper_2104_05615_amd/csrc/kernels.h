@@ -56,6 +56,7 @@ struct Batch {
 struct Sched {
   int order = 0;
   int xcd = 1;
+  int tchunk = 0;   // full-lattice hops: 0 lexicographic block order, k > 0 chunked t sweep of ~(80 << k) KB chunks
 };
 
 struct HopGeometry {

@@ -101,6 +101,46 @@ int64_t hop_full_blocks(const Lattice& lat, int Ls, Prec p) {
   return (lat.vh + ns - 1) / ns;
 }
 
+// Chunk shape of the chunked block order (BlockOrder): bzc z-planes by bb
+// blocks of a plane whose input spinors take at most `budget` bytes, with the
+// fewest neighbour planes and rows outside the chunk per site inside it
+// (2 / bzc + 2 / rows, a dimension the chunk spans whole counting 0).
+// Lexicographic order when blocks do not tile whole planes.
+static BlockOrder block_order(const Lattice& lat, int ns, int Ls, int site_bytes, int64_t budget) {
+  BlockOrder bo{};
+  bo.chunk = 0;
+  const int64_t S = lat.vh / lat.T, P = (int64_t)lat.X * lat.Y / 2, half_x = lat.X / 2;
+  if (lat.vh % lat.T || S % ns || P % ns) return bo;
+  const int64_t bz = P / ns, blk_bytes = (int64_t)ns * Ls * site_bytes;
+  double best = 1e30;
+  int64_t bbz = 0, bbb = 0;
+  for (int64_t zc = 1; zc <= lat.Z; ++zc) {
+    if (lat.Z % zc) continue;
+    for (int64_t b = 1; b <= bz; ++b) {
+      if (bz % b) continue;
+      if (b < bz && (b * ns) % half_x) continue;   // a band of whole rows
+      if (zc * b * blk_bytes > budget) continue;
+      const double halo = (zc < lat.Z ? 2.0 / zc : 0.0) + (b < bz ? 2.0 * half_x / (b * ns) : 0.0);
+      if (halo < best - 1e-12 || (halo < best + 1e-12 && zc * b > bbz * bbb)) {
+        best = halo;
+        bbz = zc;
+        bbb = b;
+      }
+    }
+  }
+  if (bbz == 0 || (bbz == lat.Z && bbb == bz)) return bo;   // whole slices: the lexicographic order
+  bo.chunk = (uint32_t)(bbz * bbb);
+  bo.bzc = (uint32_t)bbz;
+  bo.bb = (uint32_t)bbb;
+  bo.bz = (uint32_t)bz;
+  bo.bps = (uint32_t)(S / ns);
+  bo.fchunk = make_fastdiv(bo.chunk);
+  bo.fT = make_fastdiv((uint32_t)lat.T);
+  bo.fbb = make_fastdiv(bo.bb);
+  bo.fnyc = make_fastdiv((uint32_t)(bz / bbb));
+  return bo;
+}
+
 template <typename S>
 static void hop_full_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, const FieldPtr* w, const void* gauge,
                        const HopGeometry& geo, bool dagger, const Epilogue& epi, const Batch& bt, const Sched& sc) {
@@ -111,6 +151,9 @@ static void hop_full_t(hipStream_t st, const FieldPtr& out, const FieldPtr& in, 
   g.g.data = reinterpret_cast<const typename Gauge<T>::c2*>(gauge);
   g.g.vh = geo.lat.vh;
   const int ns = sites_per_block(geo.Ls, out.prec);
+  g.order.chunk = 0;
+  if (sc.tchunk > 0 && geo.lat.vh < (int64_t)1 << 31)
+    g.order = block_order(geo.lat, ns, geo.Ls, 24 * (int)sizeof(T), (int64_t)80 << (10 + sc.tchunk));
   launch_hop<FullGeo<T>, S>(st, g, (geo.lat.vh + ns - 1) / ns, out, in, w, geo.Ls, ns, dagger, epi, bt, sc);
 }
 

@@ -69,10 +69,42 @@ __device__ __forceinline__ void accumulate(const T* gh, T sc, T* acc) {
 
 // ---------------------------------------------------------------- full lattice
 
+// Order in which the site blocks of a full-lattice hop are swept.  In
+// lexicographic order the +-t neighbours of a block lie a whole time slice
+// away, and at these volumes three slices exceed an XCD's L2, so every
+// neighbour spinor of the t direction is fetched again.  The chunked order
+// cuts each time slice into chunks of bzc z-planes by bb blocks of a plane
+// and sweeps one chunk through all T slices before the next: the blocks in
+// flight together are consecutive slices of one small chunk, and the t
+// neighbours of a block were just read or are about to be.  chunk = 0 keeps
+// the lexicographic order.  A block is the same set of sites in either order
+// (only the order of the launch's workgroups changes), so no result depends
+// on it.
+struct BlockOrder {
+  uint32_t chunk;      // blocks per chunk (bzc * bb); 0: lexicographic
+  uint32_t bzc, bb;    // z-planes per chunk, blocks of one plane per chunk
+  uint32_t bz;         // blocks per z-plane
+  uint32_t bps;        // blocks per time slice
+  FastDiv fchunk, fT, fbb, fnyc;   // division by chunk, T, bb and bz / bb
+
+  __device__ __forceinline__ int64_t physical(int64_t blk) const {
+    if (chunk == 0) return blk;
+    const uint32_t L = (uint32_t)blk;
+    const uint32_t q = fchunk.div(L), w = L - q * chunk;
+    const uint32_t c = fT.div(q), t = q - c * fT.d;
+    const uint32_t zl = fbb.div(w), k = w - zl * bb;
+    const uint32_t zc = fnyc.div(c), yc = c - zc * fnyc.d;
+    return (int64_t)t * bps + (int64_t)(zc * bzc + zl) * bz + yc * bb + k;
+  }
+};
+
 template <typename T> struct FullGeo {
   Lattice lat;
   int par;        // output parity
   Gauge<T> g;
+  BlockOrder order;
+
+  __device__ __forceinline__ int64_t physical(int64_t blk) const { return order.physical(blk); }
 
   __device__ __forceinline__ SiteRef locate(int64_t blk, int sl, int ns, int Ls, int s) const {
     SiteRef r;
@@ -292,6 +324,8 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
   Lattice lat;
   int par;        // output parity (global)
   Gauge<LinkT> g;
+
+  __device__ __forceinline__ int64_t physical(int64_t blk) const { return blk; }
 
   __device__ __forceinline__ SiteRef locate(int64_t blk, int sl, int ns, int Ls, int s) const {
     SiteRef r;
@@ -728,6 +762,7 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
   int rhs;
   wk.decode(blockIdx.x, gridDim.x, blk, rhs);
   if (wk.mask && wk.mask[rhs] == 0) return;   // uniform over the workgroup
+  blk = geo.physical(blk);
   const Field<S> out = out_b.at(rhs), in = in_b.at(rhs), w = w_b.at(rhs), dotf = dotf_b.at(rhs);
   const SiteRef r = geo.locate(blk, sl, ns, Ls, s);
   const bool valid = inb && r.valid;

@@ -119,6 +119,22 @@ def test_batch_and_tuning_entry_points_validate_before_the_device():
         assert (o.value, x.value, us.value) == (0, 1, 0.0)
         assert M.mspcg_get_schedule(h, 2, 4, ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)) == M.MSPCG_OK
         assert o.value == 1
+        # block order of the full-lattice hops: chunked t sweep by default,
+        # pinned by mspcg_set_schedule; the subdomain kind keeps its order
+        t = ctypes.c_int32()
+        assert M.mspcg_get_tchunk(h, 0, 1, ctypes.byref(t)) == M.MSPCG_OK and t.value == 3
+        assert M.mspcg_get_tchunk(h, 2, 1, ctypes.byref(t)) == M.MSPCG_OK and t.value == 0
+        assert M.mspcg_set_schedule(h, 3, 1, 0, 1, 0) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_schedule(h, 0, 0, 0, 1, 0) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_schedule(h, 0, 1, 2, 1, 0) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_schedule(h, 0, 1, 0, 1, 5) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_get_tchunk(h, 0, 1, None) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_schedule(h, 1, 1, 0, 0, 1) == M.MSPCG_OK
+        assert M.mspcg_get_tchunk(h, 1, 1, ctypes.byref(t)) == M.MSPCG_OK and t.value == 1
+        assert M.mspcg_get_schedule(h, 1, 1, ctypes.byref(o), ctypes.byref(x), ctypes.byref(us)) == M.MSPCG_OK
+        assert (o.value, x.value) == (0, 0)
+        assert M.mspcg_set_schedule(h, 2, 1, 0, 1, 4) == M.MSPCG_OK
+        assert M.mspcg_get_tchunk(h, 2, 1, ctypes.byref(t)) == M.MSPCG_OK and t.value == 0
         e, a = ctypes.c_int64(), ctypes.c_int64()
         assert M.mspcg_footprint(h, 1, ctypes.byref(e), ctypes.byref(a)) == M.MSPCG_ERR_NO_PARAMS
         assert M.mspcg_share_gauge(h, h) == M.MSPCG_ERR_NO_GAUGE

@@ -404,3 +404,42 @@ def test_full_five_dimensional_solve(outer, inner):
     assert st.status == 0
     assert r < 1e-9 and abs(r - res) < 1e-11
     assert rel(psi_o, op.reconstruct_odd(psi_e, phi_o)) < 1e-12
+
+
+# ---------------------------------------------------------------- block orders
+
+def test_block_orders_of_full_lattice_hops_keep_results():
+    """The chunked time-slice sweeps of the full-lattice hops (mspcg_set_schedule,
+    tchunk 1..4) visit the same site blocks as the lexicographic order: A in
+    FP32 and FP64 and an MSPCG solve (whose <p, Ap> is fused into the last
+    hop, one partial per site block) are bit-identical under every order."""
+    from paper_2104_05615_amd import KIND_FP64, KIND_OUTER, MSPCG
+    dims, Ls, sub = (8, 8, 8, 8), 8, (4, 4, 4, 4)
+    U = W.gauge_field(dims, 0.5, 43)
+    op = oracle.MobiusDWF(U, Ls, 1.5, 0.5, 1.8, 0.1)
+    s = MSPCG(dims)
+    s.load_gauge(U)
+    s.set_mobius(Ls, 1.5, 0.5, 1.8, 0.1)
+    s.set_subdomains(sub)
+    s.set_solver(tol=1e-10, maxiter=400, inner_iters=3, inner_prec="fp16", outer_prec="fp32")
+    psi = rand_field(Ls, op.vh, 41)
+    b = W.gaussian_source(dims, Ls, 42)
+    ref = op.A(psi)
+    base, xs = {}, {}
+    for tchunk in range(5):
+        for kind in (KIND_OUTER, KIND_FP64):
+            s.set_schedule(kind, 1, order=0, xcd=1, tchunk=tchunk)
+            assert s.tchunk(kind, 1) == tchunk
+        say(f"[gpu] block order tchunk={tchunk}: A fp32/fp64, MSPCG solve")
+        for prec in ("fp32", "fp64"):
+            got = s.apply("A", prec, psi)
+            if tchunk == 0:
+                base[prec] = got
+                assert rel(got, ref) < TOL_A[prec], prec
+            else:
+                assert np.array_equal(got, base[prec]), (prec, tchunk)
+        x, st = s.solve(b)
+        assert st.status == 0
+        xs[tchunk] = x
+        assert np.array_equal(x, xs[0]), tchunk
+    s.close()
