@@ -240,7 +240,11 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
  * (inner) hop kernels, 2 = whole preconditioner applications, 3 = full-lattice
  * hop kernels in FP64 (true residuals); or one hop stage of A: 21..24 (full
  * lattice, FP32/16-bit), 31..34 (full lattice, FP64), 11..14 (subdomain hops
- * h1..h4: N1<-C, N2<-N1, N1<-N2, C<-N1).  Counters are reset by set_profiling. */
+ * h1..h4: N1<-C, N2<-N1, N1<-N2, C<-N1).  Counters are reset by set_profiling.
+ * on = 1 times every launch; on = N > 1 times one launch in N of each hop
+ * stage (every preconditioner application still), so that the average
+ * launch time comes from a sample at 1/N of the events' cost; launches then
+ * counts the timed ones.  INVALID_ARG for on < 0. */
 mspcg_status mspcg_set_profiling(mspcg_t h, int32_t on);
 mspcg_status mspcg_get_kernel_time(mspcg_t h, int32_t kind, int64_t* launches, double* ms);
 

@@ -354,8 +354,9 @@ class MSPCG:
         _check(mspcg_apply_device(self._h, OPS[op] if isinstance(op, str) else int(op),
                                   PREC[prec] if isinstance(prec, str) else int(prec), in_ptr, out_ptr, stream))
 
-    def set_profiling(self, on=True):
-        _check(mspcg_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on=True, stride=1):
+        """HIP-event timing of the hop stages; stride N > 1 times one launch in N of each stage."""
+        _check(mspcg_set_profiling(self._h, (max(1, int(stride)) if on else 0)))
 
     def kernel_time(self, kind):
         n = ctypes.c_int64()

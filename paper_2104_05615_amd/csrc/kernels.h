@@ -167,10 +167,11 @@ void ctl_after_update(hipStream_t st, const Ctl& c, double* scal, int n, const C
 //
 // Per-subdomain inner CG state: rho[d], alpha[d], beta[d], active[d].
 struct SubScalars {
-  double* rho;
+  double* rho;      // rho of the current iteration (and the one SUB_INIT / SUB_BETA write)
   double* alpha;
   double* beta;
   int* active;
+  double* rho_next; // sub_xpay5 reads rho and writes rho_next (the caller swaps them)
 };
 
 // Restrict the outer residual to the centre region of every subdomain:
@@ -178,13 +179,17 @@ struct SubScalars {
 void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_outer, const FieldPtr& rs,
                   const FieldPtr& ps, const FieldPtr& t0, const void* E, const Lattice& lat, const SubTables& tc,
                   int nsub, int Ls, double* partial, const Batch& bt = Batch());
-// z_s (+)= alpha_d p_s ; r_s -= alpha_d q_s ; partial |r_s|^2  (first: z_s = alpha_d p_s)
+// alpha_d = rho_d / <p_s, q_s> from the [d][bps] partials pq (SUB_ALPHA, computed
+// by every wavefront), then z_s (+)= alpha_d p_s ; r_s -= alpha_d q_s ;
+// partial |r_s|^2  (first: z_s = alpha_d p_s)
 void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
                 const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
-                double* partial, const Batch& bt = Batch());
-// p_s = r_s + beta_d p_s ; t0 = E p_s
+                const double* pq, double* partial, const Batch& bt = Batch());
+// beta_d = |r_s|^2 / rho_d from the [d][bps] partials rr (SUB_BETA, computed by
+// every wavefront; rho_next = |r_s|^2), then p_s = r_s + beta_d p_s ; t0 = E p_s
 void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0,
-               const SubScalars& sc, const void* E, const SubTables& tc, int nsub, int Ls, const Batch& bt = Batch());
+               const SubScalars& sc, const double* rr, const void* E, const SubTables& tc, int nsub, int Ls,
+               const Batch& bt = Batch());
 // z = sum_s R_s^T z_s (outer precision); partials Re<z, r>, Re<z, r_old> (r_old nullable)
 void sub_prolong(hipStream_t st, Prec outer, Prec inner, const FieldPtr& z_outer, const FieldPtr& zs,
                  const FieldPtr& r_outer, const FieldPtr* rold_outer, const Lattice& lat, const SubTables& tc,

@@ -556,8 +556,15 @@ struct mspcg_ctx {
   }
 
   // ---------------------------------------------------------------- profiling
+  // profiling kinds below 64 of which every prof_stride-th launch is timed
+  // (the whole-preconditioner kind 2 always): the average launch time then
+  // comes from a sample at a fraction of the events' cost
+  int prof_stride = 1;
+  int64_t prof_count[64] = {};
   size_t ev_begin(hipStream_t st, int kind) {
     if (!profiling) return (size_t)-1;
+    if (prof_stride > 1 && kind != 2 && kind >= 0 && kind < 64 && prof_count[kind]++ % prof_stride != 0)
+      return (size_t)-1;
     if (ev_used == ev_pool.size()) {
       EventPair e;
       HIPCHK(hipEventCreate(&e.a));
@@ -698,6 +705,7 @@ struct mspcg_ctx {
              qs = field("in.q", I, nc, nb), t0 = field("in.t0", I, nc, nb);
     SubScalars sc;
     sc.rho = buf("in.rho", (size_t)nb * nsub * sizeof(double)).as<double>();
+    sc.rho_next = buf("in.rho2", (size_t)nb * nsub * sizeof(double)).as<double>();
     sc.alpha = buf("in.alpha", (size_t)nb * nsub * sizeof(double)).as<double>();
     sc.beta = buf("in.beta", (size_t)nb * nsub * sizeof(double)).as<double>();
     sc.active = buf("in.active", (size_t)nb * nsub * sizeof(int)).as<int>();
@@ -706,12 +714,17 @@ struct mspcg_ctx {
     double* ppap = partial("in.pap", (int64_t)nb * nsub * tc.bps);
     sub_restrict(st, O, I, r, rs, ps, t0, mat(I, MAT_MPHI), lat, tc, nsub, Ls, prr, bt);
     sub_finish(st, prr, tc.bps, nsub, sc, SUB_INIT, bt);
+    // the per-subdomain alpha and beta are formed inside the kernels that
+    // use them (sub_update, sub_xpay5) from the partials of the kernel
+    // before; rho alternates between two arrays so that no block of
+    // sub_xpay5 overwrites the rho another block still reads
     for (int it = 0; it < k; ++it) {
-      if (it > 0) sub_xpay5(st, I, ps, rs, t0, sc, mat(I, MAT_MPHI), tc, nsub, Ls, bt);
+      if (it > 0) {
+        sub_xpay5(st, I, ps, rs, t0, sc, prr, mat(I, MAT_MPHI), tc, nsub, Ls, bt);
+        std::swap(sc.rho, sc.rho_next);
+      }
       Asub(st, I, qs, ps, t0, ppap, bt);
-      sub_finish(st, ppap, tc.bps, nsub, sc, SUB_ALPHA, bt);
-      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, prr, bt);
-      sub_finish(st, prr, tc.bps, nsub, sc, SUB_BETA, bt);
+      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, ppap, prr, bt);
     }
     sub_prolong(st, O, I, z, zs, r, rold, lat, tc, nsub, Ls, pz1, pz2, bt);
     ev_end(st, ev);
@@ -1649,7 +1662,7 @@ int64_t estimate_solve_bytes(const mspcg_ctx* h, int nrhs) {
     n += 5 * fbytes(I, nc5);
     n += fbytes(I, (int64_t)h->nsub * h->nN1 * Ls) + fbytes(I, (int64_t)h->nsub * h->nN2 * Ls);
     parts += 4 * (int64_t)h->nsub * bps;
-    n += (int64_t)h->nsub * (3 * 8 + 4);
+    n += (int64_t)h->nsub * (4 * 8 + 4);   // rho (two arrays), alpha, beta, active
   } else {
     parts += 2 * nbl;
   }
@@ -2139,7 +2152,10 @@ mspcg_status mspcg_set_profiling(mspcg_t h, int32_t on) {
   return guarded([&]() -> mspcg_status {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
     if (h->hip_ready) HIPCHK(hipStreamSynchronize(h->stream));
+    if (on < 0) throw Error(MSPCG_ERR_INVALID_ARG, "on must be >= 0");
     h->profiling = on != 0;
+    h->prof_stride = on > 1 ? on : 1;
+    for (int64_t& c : h->prof_count) c = 0;
     h->ev_used = 0;
     h->ev_log.clear();
     return MSPCG_OK;

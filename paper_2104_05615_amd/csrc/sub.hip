@@ -92,10 +92,49 @@ k_sub_restrict(Field<O> r, Field<I> rs, Field<I> ps, Field<I> t0, const calc_t<I
   if (threadIdx.x == 0) partial[c.blk] = tot;
 }
 
+// The scalar a k_sub_finish of mode SUB_ALPHA or SUB_BETA would compute for
+// subdomain d, evaluated in the kernel that uses it: every wavefront sums
+// the bps partials in k_sub_finish's fixed order (lane-strided, then a
+// butterfly), so each gets the same value to the bit without a barrier, and
+// the field loads of the kernel need not wait for it.  Thread 0 of the block
+// holding the subdomain's first site block also stores the new state (alpha
+// or beta, rho_next, active) as k_sub_finish does.  Other wavefronts may
+// read `active` while that thread clears it, but it is cleared only where
+// every reader takes the same decision from the same sum; rho is read from
+// one array and written to another.  Call from every lane of the wavefront.
+__device__ __forceinline__ double fused_finish(const double* partial, int bps, int64_t d, bool first_blk, int mode,
+                                               const double* rho, double* rho_next, double* alpha, double* beta,
+                                               int* active) {
+  const int lane = threadIdx.x & 63;
+  double S = 0;
+  for (int b = lane; b < bps; b += 64) S += partial[d * bps + b];
+  for (int off = 32; off > 0; off >>= 1) S += __shfl_xor(S, off);
+  const bool act = active[d] != 0;
+  const bool store = first_blk && threadIdx.x == 0;
+  double v;
+  if (mode == SUB_ALPHA) {
+    const bool ok = act && S > 0.0 && isfinite(S);
+    v = ok ? rho[d] / S : 0.0;
+    if (store) {
+      alpha[d] = v;
+      if (!ok) active[d] = 0;
+    }
+  } else {
+    const bool ok = act && S > 0.0;
+    v = ok ? S / rho[d] : 0.0;
+    if (store) {
+      beta[d] = v;
+      rho_next[d] = ok ? S : rho[d];
+      if (!ok) active[d] = 0;
+    }
+  }
+  return v;
+}
+
 template <typename I>
 __global__ void __launch_bounds__(256)
-k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* alpha, int nsub, int first,
-             SubTables tc, int Ls, int ns, double* partial, const int* mask) {
+k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, SubScalars sc, int nsub, int first,
+             SubTables tc, int Ls, int ns, const double* pq, double* partial, const int* mask) {
   using T = calc_t<I>;
   __shared__ double red[16];
   const int rhs = blockIdx.y;
@@ -104,12 +143,14 @@ k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* a
   ps = ps.at(rhs);
   rs = rs.at(rhs);
   qs = qs.at(rhs);
-  alpha += (int64_t)rhs * nsub;
+  const int64_t so = (int64_t)rhs * nsub;
   partial += (int64_t)rhs * gridDim.x;
   const CSite c = c_site(tc, ns, Ls);
+  const double alpha_d = fused_finish(pq + so * tc.bps, tc.bps, c.d, c.blk == c.d * tc.bps, SUB_ALPHA, sc.rho + so,
+                                      nullptr, sc.alpha + so, nullptr, sc.active + so);
   double loc = 0;
   if (c.valid) {
-    const T a = (T)alpha[c.d];
+    const T a = (T)alpha_d;
     T z[24], p[24], r[24], q[24];
     load_site(ps, c.in5, p);
     load_site(rs, c.in5, r);
@@ -136,24 +177,26 @@ k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, const double* a
 
 template <typename I>
 __global__ void __launch_bounds__(256)
-k_sub_xpay5(Field<I> ps, Field<I> rs, Field<I> t0, const double* beta, int nsub, const calc_t<I>* E, SubTables tc,
-            int Ls, int ns, const int* mask) {
+k_sub_xpay5(Field<I> ps, Field<I> rs, Field<I> t0, SubScalars sc, const double* rr, int nsub, const calc_t<I>* E,
+            SubTables tc, int Ls, int ns, const int* mask) {
   using T = calc_t<I>;
   const int rhs = blockIdx.y;
   if (mask && mask[rhs] == 0) return;
   ps = ps.at(rhs);
   rs = rs.at(rhs);
   t0 = t0.at(rhs);
-  beta += (int64_t)rhs * nsub;
+  const int64_t so = (int64_t)rhs * nsub;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* red = reinterpret_cast<double*>(lds_raw);
   T* mats = reinterpret_cast<T*>(red + 16);
   T* tile = mats + 2 * Ls * Ls;
   const CSite c = c_site(tc, ns, Ls);
   for (int k = threadIdx.x; k < 2 * Ls * Ls; k += blockDim.x) mats[k] = E[k];
+  const double beta_d = fused_finish(rr + so * tc.bps, tc.bps, c.d, c.blk == c.d * tc.bps, SUB_BETA, sc.rho + so,
+                                     sc.rho_next + so, nullptr, sc.beta + so, sc.active + so);
   T p[24];
   if (c.valid) {
-    const T b = (T)beta[c.d];
+    const T b = (T)beta_d;
     T r[24];
     load_site(ps, c.in5, p);
     load_site(rs, c.in5, r);
@@ -292,46 +335,47 @@ void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_oute
 
 template <typename I>
 static void update_t(hipStream_t st, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& qs,
-                     const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls, double* partial,
-                     const Batch& bt) {
+                     const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls, const double* pq,
+                     double* partial, const Batch& bt) {
   const int ns = c_ns(Ls, zs.prec);
   hipLaunchKernelGGL((k_sub_update<I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), 0, st, typed<I>(zs),
-                     typed<I>(ps), typed<I>(rs), typed<I>(qs), sc.alpha, nsub, first ? 1 : 0, tc, Ls, ns, partial,
+                     typed<I>(ps), typed<I>(rs), typed<I>(qs), sc, nsub, first ? 1 : 0, tc, Ls, ns, pq, partial,
                      bt.mask);
   LAUNCH_CHECK();
 }
 
 void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
                 const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
-                double* partial, const Batch& bt) {
+                const double* pq, double* partial, const Batch& bt) {
   switch (inner) {
-    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
-    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
-    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
-    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
-    case Prec::I8: update_t<int8_t>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, partial, bt); break;
+    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::I8: update_t<int8_t>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
   }
 }
 
 template <typename I>
 static void xpay5_t(hipStream_t st, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0, const SubScalars& sc,
-                    const void* E, const SubTables& tc, int nsub, int Ls, const Batch& bt) {
+                    const double* rr, const void* E, const SubTables& tc, int nsub, int Ls, const Batch& bt) {
   using T = calc_t<I>;
   const int ns = c_ns(Ls, ps.prec);
   const size_t lds = 16 * sizeof(double) + sizeof(T) * (size_t)(2 * Ls * Ls + ns * tile_stride(Ls));
   hipLaunchKernelGGL((k_sub_xpay5<I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), lds, st, typed<I>(ps),
-                     typed<I>(rs), typed<I>(t0), sc.beta, nsub, (const T*)E, tc, Ls, ns, bt.mask);
+                     typed<I>(rs), typed<I>(t0), sc, rr, nsub, (const T*)E, tc, Ls, ns, bt.mask);
   LAUNCH_CHECK();
 }
 
 void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0,
-               const SubScalars& sc, const void* E, const SubTables& tc, int nsub, int Ls, const Batch& bt) {
+               const SubScalars& sc, const double* rr, const void* E, const SubTables& tc, int nsub, int Ls,
+               const Batch& bt) {
   switch (inner) {
-    case Prec::F64: xpay5_t<double>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
-    case Prec::F32: xpay5_t<float>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
-    case Prec::F16: xpay5_t<__half>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
-    case Prec::BF16: xpay5_t<__hip_bfloat16>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
-    case Prec::I8: xpay5_t<int8_t>(st, ps, rs, t0, sc, E, tc, nsub, Ls, bt); break;
+    case Prec::F64: xpay5_t<double>(st, ps, rs, t0, sc, rr, E, tc, nsub, Ls, bt); break;
+    case Prec::F32: xpay5_t<float>(st, ps, rs, t0, sc, rr, E, tc, nsub, Ls, bt); break;
+    case Prec::F16: xpay5_t<__half>(st, ps, rs, t0, sc, rr, E, tc, nsub, Ls, bt); break;
+    case Prec::BF16: xpay5_t<__hip_bfloat16>(st, ps, rs, t0, sc, rr, E, tc, nsub, Ls, bt); break;
+    case Prec::I8: xpay5_t<int8_t>(st, ps, rs, t0, sc, rr, E, tc, nsub, Ls, bt); break;
   }
 }
 

@@ -135,6 +135,8 @@ def test_batch_and_tuning_entry_points_validate_before_the_device():
         assert (o.value, x.value) == (0, 0)
         assert M.mspcg_set_schedule(h, 2, 1, 0, 1, 4) == M.MSPCG_OK
         assert M.mspcg_get_tchunk(h, 2, 1, ctypes.byref(t)) == M.MSPCG_OK and t.value == 0
+        assert M.mspcg_set_profiling(h, -1) == M.MSPCG_ERR_INVALID_ARG
+        assert M.mspcg_set_profiling(h, 8) == M.MSPCG_OK and M.mspcg_set_profiling(h, 0) == M.MSPCG_OK
         e, a = ctypes.c_int64(), ctypes.c_int64()
         assert M.mspcg_footprint(h, 1, ctypes.byref(e), ctypes.byref(a)) == M.MSPCG_ERR_NO_PARAMS
         assert M.mspcg_share_gauge(h, h) == M.MSPCG_ERR_NO_GAUGE

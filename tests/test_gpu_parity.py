@@ -350,6 +350,16 @@ def test_profiling_counters():
     s.set_profiling(False)
     assert n0 >= 4 * st.outer_iters and ms0 > 0
     assert n1 == 4 * 3 * st.outer_iters and ms1 > 0
+    # sampled: one launch in 4 of each subdomain hop stage (3 inner
+    # iterations per outer one, each stage once per inner iteration)
+    s.set_profiling(True, stride=4)
+    say("[gpu] profiled solve, one launch in 4")
+    x2, st2 = s.solve(W.gaussian_source(dims, Ls, 91))
+    n1s, ms1s = s.kernel_time(1)
+    n12, _ = s.kernel_time(12)
+    s.set_profiling(False)
+    assert np.array_equal(x2, x) and st2.outer_iters == st.outer_iters
+    assert n12 == (3 * st.outer_iters + 3) // 4 and n1s == 4 * n12 and ms1s > 0
 
 
 # ---------------------------------------------------------------- vector-ALU epilogue
