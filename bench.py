@@ -254,8 +254,8 @@ def batch_bench(args):
         log(f"[batch] {inner}: {n} single solves {t_seq:.2f}s, iters {[a.outer_iters for a in seq]}")
         x_seq = xt.clone()
         s.autotune(n)
-        sched = {k: s.schedule(kk, n) for k, kk in (("outer", KIND_OUTER), ("fp64", KIND_FP64),
-                                                  ("inner", KIND_INNER))}
+        sched = {k: s.schedule(kk, n) + (s.tchunk(kk, n),) for k, kk in (("outer", KIND_OUTER), ("fp64", KIND_FP64),
+                                                                       ("inner", KIND_INNER))}
         torch.cuda.synchronize()
         t = time.perf_counter()
         st, stats = s.solve_batch_device(n, bt.data_ptr(), xt.data_ptr())
@@ -268,7 +268,8 @@ def batch_bench(args):
                       "outer_iters": [a.outer_iters for a in stats],
                       "true_rel_resid_max": max(a.true_rel_resid for a in stats),
                       "identical_to_single_solves": same,
-                      "schedule": {k: {"order": v[0], "xcd": v[1], "four_hops_us": v[2]} for k, v in sched.items()}}
+                      "schedule": {k: {"order": v[0], "xcd": v[1], "tchunk": v[3], "four_hops_us": v[2]}
+                                   for k, v in sched.items()}}
     out["value"] = out["fp16"]["batched_s"]
     print(json.dumps(out), flush=True)
 
