@@ -903,12 +903,24 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
         for (int j = 0; j < NJ; ++j) accs[j] = tile(j * NW >= 12 ? 1 : 0, j * NW, ra);
         __syncthreads();
         T* ob = tileA + col * tile_stride(Ls) + w;
+        if ((Ls & 3) == 0) {
+          // Ls a multiple of 4: a lane's four rows are all valid or all
+          // beyond Ls, so one branch covers every store
+          if (4 * g < Ls) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
+            for (int j = 0; j < NJ; ++j) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int t = 4 * g + v;
-            if (t < Ls) ob[t * 24 + j * NW] = (T)(accs[j][v] * cs);
+              for (int v = 0; v < 4; ++v) ob[(4 * g + v) * 24 + j * NW] = (T)(accs[j][v] * cs);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int t = 4 * g + v;
+              if (t < Ls) ob[t * 24 + j * NW] = (T)(accs[j][v] * cs);
+            }
           }
         }
       };
