@@ -844,7 +844,12 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
     float cs = 1.f, ics = 1.f;
     if (HO) {
       cs = 0.f;
-      for (int t = 0; t < Ls; ++t) cs = fmaxf(cs, smax[col * Ls + t]);
+      const float* sm = smax + col * Ls;
+      if ((Ls & 3) == 0) {
+        for (int t = 0; t < Ls; t += 4) cs = fmaxf(cs, fmaxf(fmaxf(sm[t], sm[t + 1]), fmaxf(sm[t + 2], sm[t + 3])));
+      } else {
+        for (int t = 0; t < Ls; ++t) cs = fmaxf(cs, sm[t]);
+      }
       ics = cs > 0.f ? 1.f / cs : 0.f;
     }
     if (E1 || e0_dense) {
