@@ -109,7 +109,9 @@ typedef struct {
 
 /* Create a handle for an X*Y*Z*T lattice on HIP device `device`.  No HIP call
  * is made here; the device is touched by the first call that needs it.
- * Errors: INVALID_ARG if out is NULL, an extent is < 2 or odd, or device < 0. */
+ * Errors: INVALID_ARG if out is NULL, an extent is < 2 or odd, device < 0,
+ * the volume is 2^31 sites or more, or the FP64 gauge records (V * 640
+ * bytes) reach 4 GiB (see the size limits under mspcg_set_mobius). */
 mspcg_status mspcg_create(mspcg_t* out, const int32_t dims[4], int32_t device);
 
 /* Free the handle and everything it owns.  NULL is accepted. */
@@ -122,7 +124,18 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U);
 
 /* Mobius parameters of M5 and M_phi (Sec. 2.2 with the Mobius construction the
  * paper cites): fifth-dimension extent Ls >= 2, b, c, domain-wall height M5,
- * quark mass mf.  Errors: INVALID_ARG for Ls < 2 or Ls > 32, or a singular M5. */
+ * quark mass mf.  Errors: INVALID_ARG for Ls < 2 or Ls > 32, a singular M5,
+ * or an FP64 5D field (V/2 * Ls * 192 bytes) of 4 GiB or more.
+ *
+ * Size limits (32-bit addressing of the kernels: buffer ranges and per-lane
+ * byte offsets are 32-bit): every array of one right-hand side must stay
+ * below 4 GiB -- the FP64 gauge record array (V * 640 bytes, checked by
+ * mspcg_create together with V < 2^31), an FP64 5D field (checked here) and
+ * the largest subdomain region field, nsub * |N2| * Ls * (192, 96, 48 or 24
+ * bytes for FP64, FP32, FP16/BF16, INT8 inner storage; checked by
+ * set_subdomains, set_solver and every solve and apply, also for the
+ * precision an apply names).  A batch of right-hand sides may exceed 4 GiB
+ * in total. */
 mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double M5, double mf);
 
 /* Subdomain extents (X, Y, Z, T) of the virtual block decomposition used by the
@@ -134,14 +147,21 @@ mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double 
 mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]);
 
 /* Solver parameters (copied).  Errors: INVALID_ARG for tol <= 0, maxiter < 1,
- * inner_iters < 0, outer_prec not FP64/FP32, an unknown precision or beta rule. */
+ * inner_iters < 0, outer_prec not FP64/FP32, an unknown precision or beta rule,
+ * or an inner precision whose subdomain region field would reach 4 GiB with
+ * the tiling and Ls already set. */
 mspcg_status mspcg_set_solver(mspcg_t h, const mspcg_solver_params* p);
 
 /* Solve A x = b (A = D^dag D, eq. normal_equation) for one right-hand side.
  * b, x: host FP64 even fields [Ls][V/2][4][3]; x0 (nullable) is the starting
  * guess (r0 = b - A x0), else 0.  Synchronous.  st (nullable) gets the stats.
  * Returns OK, NOT_CONVERGED (maxiter reached; x is the last iterate),
- * BREAKDOWN (NaN/Inf), NO_GAUGE, NO_PARAMS, BAD_TILING (MSPCG without a tiling). */
+ * BREAKDOWN (NaN/Inf or <p, A p> <= 0: x is the last iterate whose values are
+ * finite -- with FP32 outer precision the solution of the last reliable
+ * update when the breaking step is not finite -- and st->true_rel_resid its
+ * true residual), NO_GAUGE, NO_PARAMS, BAD_TILING (MSPCG without a tiling).
+ * INVALID_ARG when a field would exceed the 32-bit addressing limits (see
+ * mspcg_set_mobius). */
 mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0, mspcg_stats* st);
 
 /* As mspcg_solve with device FP64 buffers b, x (layout above), x0 nullable.
@@ -179,6 +199,9 @@ mspcg_status mspcg_solve_full_device(mspcg_t h, const double* phi, double* psi, 
  *          (RHS r at offset r * Ls * V/2 * 24 doubles);  x0: nullable, same.
  *   st:    nullable, else an array of nrhs stats (status per RHS).
  * Runs on hip_stream (NULL = the handle's stream); returns when done.
+ * A RHS that breaks down returns the solution of its last reliable update
+ * (its FP32 progress after that is dropped) and its iterated residual at the
+ * breakdown as true_rel_resid.
  * Returns BREAKDOWN if any RHS broke down, else NOT_CONVERGED if any did not
  * converge, else OK; INVALID_ARG for nrhs outside [1, 1024] or NULL buffers;
  * NO_GAUGE, NO_PARAMS, BAD_TILING as mspcg_solve. */
@@ -295,9 +318,11 @@ mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32
 
 /* Engine of the fifth-dimension epilogue of the FP32 and 16-bit site kernels
  * with Ls <= 16, for every handle of the process: 1 = MFMA (the default),
- * 0 = vector ALUs.  Call it while no handle has work in flight; handles
- * created before the call keep workspaces sized for the previous engine
- * until set_mobius or set_subdomains.  Never fails. */
+ * 0 = vector ALUs.  It waits until no solve, apply, autotune or reduced-Ls
+ * training call of any handle is running (those hold the engine for their
+ * duration), so a call never sees the engine change under it; work that an
+ * apply_device call has enqueued keeps the engine it was launched with.
+ * Partial-sum buffers grow on the next call that needs them.  Never fails. */
 mspcg_status mspcg_set_mfma(int32_t on);
 
 /* Progress of long solves: one line on stderr every `every` outer

@@ -50,6 +50,11 @@ struct Error : std::runtime_error {
 // threads and handles: captures hold the shared side of this lock, such
 // calls the exclusive side.  A thread that is capturing allocates nothing.
 std::shared_mutex g_capture_gate;
+// Calls that size workspaces or launch kernels hold this shared for their
+// duration; mspcg_set_mfma, which changes the epilogue engine and with it the
+// sites per workgroup that every launch and partial buffer is sized for,
+// takes it exclusively, so it waits until no such call is running.
+std::shared_mutex g_engine_gate;
 thread_local bool tl_capturing = false;
 
 struct DevBuf {
@@ -206,6 +211,33 @@ bool tiling_valid(const int* dims, const int* sub, std::string& why) {
     }
   }
   return true;
+}
+
+// 32-bit addressing limits of the kernels.  Fields and link arrays are
+// read through buffer resources whose range (num_records) and per-lane byte
+// offsets are 32-bit, lattice coordinates are recovered from a 32-bit
+// lexicographic index by multiply-high division (exact below 2^31), and 5D
+// indices of one right-hand side are 32-bit.  Every array of one RHS must
+// therefore stay below 4 GiB and the 4D volume below 2^31 sites.
+constexpr uint64_t kMaxArrayBytes = (1ull << 32) - 1;
+
+// checks what is known: dims always; Ls > 0: full-lattice FP64 fields (the
+// reliable updates always hold some); nN2 > 0 with Ls > 0: the largest
+// subdomain region field of inner storage `inner`
+void check_limits(const int* dims, int Ls, int64_t nsub, int64_t nN2, int inner) {
+  const uint64_t V = (uint64_t)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V >= (1ull << 31)) throw Error(MSPCG_ERR_INVALID_ARG, "lattice volume must be below 2^31 sites");
+  const uint64_t vh = V / 2;
+  if (vh * 4 * 10 * 16 * 2 > kMaxArrayBytes)
+    throw Error(MSPCG_ERR_INVALID_ARG, "FP64 gauge field of this lattice exceeds 4 GiB (32-bit buffer addressing)");
+  if (Ls > 0 && vh * (uint64_t)Ls * 192 > kMaxArrayBytes)
+    throw Error(MSPCG_ERR_INVALID_ARG, "an FP64 field of this lattice and Ls exceeds 4 GiB (32-bit buffer addressing)");
+  if (Ls > 0 && nN2 > 0 && inner >= 0) {
+    const uint64_t cb = inner == MSPCG_FP64 ? 192 : inner == MSPCG_FP32 ? 96 : inner == MSPCG_INT8 ? 24 : 48;
+    if ((uint64_t)nsub * (uint64_t)nN2 * (uint64_t)Ls * cb > kMaxArrayBytes)
+      throw Error(MSPCG_ERR_INVALID_ARG,
+                  "a subdomain region field of this tiling, Ls and inner precision exceeds 4 GiB (32-bit buffer addressing)");
+  }
 }
 
 HostTables build_tables(const int* dims, const int* sub) {
@@ -1135,8 +1167,16 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
       const double pap = h->h_scal[SLOT_PAP];
       rr = h->h_scal[SLOT_RR];
       if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(rr)) {
+        // x is returned as the last iterate whose values are finite, with its
+        // true residual: the breaking step is kept when its alpha and residual
+        // are finite (FP32: the low-order part is folded into x_hi), else
+        // (FP32) x_hi holds the solution of the last reliable update
         status = MSPCG_ERR_BREAKDOWN;
         S.iter_rel_resid = std::sqrt(std::fabs(rr)) / bnorm;
+        const double alpha = h->h_scal[SLOT_ALPHA];
+        if (O == Prec::F32 && std::isfinite(alpha) && std::isfinite(rr))
+          accum_lo(st, (double*)x64.data, (float*)x.data, n5);
+        rr = true_residual();
         break;
       }
       const double rn = std::sqrt(rr);
@@ -1177,9 +1217,6 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
       xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_BETA, h->mat(O, MAT_MPHI), vh, Ls);
     }
     S.outer_iters = it;
-    if (O == Prec::F32 && status != MSPCG_OK && status != MSPCG_ERR_BREAKDOWN) {
-      // x_hi already holds the accumulated solution after the final reliable update
-    }
     S.true_rel_resid = std::sqrt(std::fabs(rr)) / bnorm;
   }
   S.status = status;
@@ -1718,6 +1755,7 @@ void apply_impl(mspcg_ctx* h, int op, Prec P, const double* in_dev, double* out_
 void need_state(mspcg_ctx* h) {
   if (!h->have_gauge) throw Error(MSPCG_ERR_NO_GAUGE, "no gauge field loaded");
   if (!h->have_params) throw Error(MSPCG_ERR_NO_PARAMS, "Mobius parameters not set");
+  check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)h->sp.inner_prec);
 }
 
 template <typename F> mspcg_status guarded(F&& f) {
@@ -1752,6 +1790,7 @@ mspcg_status mspcg_create(mspcg_t* out, const int32_t dims[4], int32_t device) {
     for (int m = 0; m < 4; ++m)
       if (dims[m] < 2 || dims[m] % 2 || dims[m] > 32000) throw Error(MSPCG_ERR_INVALID_ARG, "lattice extents must be even and >= 2");
     if (device < 0) throw Error(MSPCG_ERR_INVALID_ARG, "device must be >= 0");
+    check_limits(dims, 0, 0, 0, -1);
     *out = new mspcg_ctx(dims, device);
     return MSPCG_OK;
   });
@@ -1795,6 +1834,8 @@ mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double 
     if (Ls < 2 || Ls > 32) throw Error(MSPCG_ERR_INVALID_ARG, "Ls must be in [2, 32]");
     if (!std::isfinite(b) || !std::isfinite(c) || !std::isfinite(M5) || !std::isfinite(mf))
       throw Error(MSPCG_ERR_INVALID_ARG, "non-finite Mobius parameter");
+    check_limits(h->dims, Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0,
+                 h->have_solver ? (int)h->sp.inner_prec : -1);
     Mats M = build_mats(Ls, b, c, M5, mf);
     h->ensure_hip();
     h->invalidate_workspace();
@@ -1826,6 +1867,12 @@ mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
     std::string why;
     if (!tiling_valid(h->dims, s, why)) throw Error(MSPCG_ERR_BAD_TILING, why);
     HostTables H = build_tables(h->dims, s);
+    {
+      int64_t ns = 1;
+      for (int m = 0; m < 4; ++m) ns *= h->dims[m] / s[m];
+      check_limits(h->dims, h->have_params ? h->Ls : 0, ns, (int64_t)H.N2.coords.size(),
+                   h->have_solver ? (int)h->sp.inner_prec : -1);
+    }
     h->ensure_hip();
     h->invalidate_workspace();
     auto up = [&](DevBuf& d, const void* src, size_t bytes) {
@@ -1876,6 +1923,8 @@ mspcg_status mspcg_set_solver(mspcg_t h, const mspcg_solver_params* p) {
     (void)to_prec(p->inner_prec);
     if (p->beta_rule != 0 && p->beta_rule != 1) throw Error(MSPCG_ERR_INVALID_ARG, "beta_rule must be 0 or 1");
     if (!(p->reliable_delta >= 0) || p->reliable_delta >= 1) throw Error(MSPCG_ERR_INVALID_ARG, "reliable_delta in [0, 1)");
+    check_limits(h->dims, h->have_params ? h->Ls : 0, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0,
+                 (int)p->inner_prec);
     h->sp = *p;
     h->have_solver = true;
     return MSPCG_OK;
@@ -1887,6 +1936,7 @@ mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const dou
   return guarded([&]() -> mspcg_status {
     if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
     return solve_impl(h, b, x, x0, s, st);
@@ -1897,6 +1947,7 @@ mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0
   return guarded([&]() -> mspcg_status {
     if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
     const size_t bytes = (size_t)h->n5() * 24 * sizeof(double);
     DevBuf db, dx, dx0;
@@ -1918,6 +1969,7 @@ mspcg_status mspcg_solve_full_device(mspcg_t h, const double* phi, double* psi, 
   return guarded([&]() -> mspcg_status {
     if (!h || !phi || !psi) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
     return solve_full_impl(h, phi, psi, s, st, full_rel_resid);
@@ -1930,6 +1982,7 @@ mspcg_status mspcg_solve_batch_device(mspcg_t h, int32_t nrhs, const double* b, 
     if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
     if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
     return solve_batch_impl(h, nrhs, b, x, x0, s, st);
@@ -1997,6 +2050,7 @@ mspcg_status mspcg_reduced_loss(mspcg_t h, int32_t nvec, const double* v, double
     if (!h || !v || !chi2) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
     if (nvec < 1) throw Error(MSPCG_ERR_INVALID_ARG, "nvec must be >= 1");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     if (h->Lh == 0) throw Error(MSPCG_ERR_INVALID_ARG, "no reduced-Ls preconditioner set");
     if (!h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "needs mspcg_set_subdomains");
     h->ensure_hip();
@@ -2014,6 +2068,7 @@ mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32
     if (nvec < 1 || iters < 0) throw Error(MSPCG_ERR_INVALID_ARG, "nvec must be >= 1 and iters >= 0");
     if (!std::isfinite(momentum)) throw Error(MSPCG_ERR_INVALID_ARG, "non-finite momentum");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     if (h->Lh == 0) throw Error(MSPCG_ERR_INVALID_ARG, "no reduced-Ls preconditioner set");
     if (!h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "needs mspcg_set_subdomains");
     h->ensure_hip();
@@ -2024,6 +2079,7 @@ mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32
 
 mspcg_status mspcg_set_mfma(int32_t on) {
   return guarded([&]() -> mspcg_status {
+    std::unique_lock<std::shared_mutex> lk(g_engine_gate);
     set_mfma_epilogue(on != 0);
     return MSPCG_OK;
   });
@@ -2062,6 +2118,7 @@ mspcg_status mspcg_autotune(mspcg_t h, int32_t nrhs) {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
     if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
     autotune_impl(h, nrhs, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -2124,6 +2181,8 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
     if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
+    check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
     h->ensure_hip();
     apply_impl(h, op, P, in, out, hip_stream ? (hipStream_t)hip_stream : h->stream);
     return MSPCG_OK;
@@ -2136,6 +2195,8 @@ mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* i
     if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
+    check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
     h->ensure_hip();
     const size_t bytes = (size_t)h->n5() * 24 * sizeof(double);
     DevBuf di, dout;

@@ -190,3 +190,25 @@ def test_reduced_ls_entry_points_validate_before_the_device():
         assert M.mspcg_train_reduced(h, 1, buf, 2, float("nan"), None) == M.MSPCG_ERR_INVALID_ARG
     finally:
         M.mspcg_destroy(h)
+
+
+def test_32bit_addressing_limits_are_rejected_before_the_device():
+    """Every array of one right-hand side is addressed with 32-bit buffer
+    ranges and offsets: sizes that would wrap are refused with INVALID_ARG
+    before any device work (the full-size positive cases run on the GPU)."""
+    import paper_2104_05615_amd as M
+    h = ctypes.c_void_p()
+    # 48^3 x 96: the FP64 link records (V * 640 bytes = 6.8 GB) exceed 4 GiB
+    assert M.mspcg_create(ctypes.byref(h), (ctypes.c_int32 * 4)(48, 48, 48, 96), 0) == M.MSPCG_ERR_INVALID_ARG
+    assert "4 GiB" in M.mspcg_last_error().decode()
+    # 1290^4 sites would overflow the 32-bit lexicographic index
+    assert M.mspcg_create(ctypes.byref(h), (ctypes.c_int32 * 4)(1290, 1290, 1290, 1290), 0) == M.MSPCG_ERR_INVALID_ARG
+    assert "2^31" in M.mspcg_last_error().decode()
+    # 32^3 x 64 fits (FP64 links 1.3 GB) ...
+    assert M.mspcg_create(ctypes.byref(h), (ctypes.c_int32 * 4)(32, 32, 32, 64), 0) == M.MSPCG_OK
+    try:
+        # ... but not with Ls = 32: an FP64 5D field is 6.4 GB
+        assert M.mspcg_set_mobius(h, 32, 1.5, 0.5, 1.8, 0.1) == M.MSPCG_ERR_INVALID_ARG
+        assert "FP64 field" in M.mspcg_last_error().decode()
+    finally:
+        M.mspcg_destroy(h)

@@ -248,3 +248,40 @@ def test_mspcg_fewer_outer_iterations_and_gauge_invariant_history():
     n = min(len(i_ms.history), len(i_g.history), 15)
     h1, h2 = np.array(i_ms.history[:n]), np.array(i_g.history[:n])
     assert np.max(np.abs(h1 - h2) / h1) < 1e-9
+
+
+def _successive_conjugacy(op, til, b, k, beta_rule, iters=8):
+    """max over outer iterations of |Re<p_{j+1}, A p_j>| / (|p_{j+1}|_A |p_j|_A)
+    for Alg. 1 with the k-step inner-CG preconditioner.  The search
+    directions are read off the iterates: x_j - x_{j-1} = alpha_j p_j, and the
+    ratio is invariant under the scale alpha_j."""
+    xs = [np.zeros_like(b)]
+    oracle.pcg(op, b, 1e-30, iters, precond=lambda r: oracle.precondition(op, til, r, k),
+               beta_rule=beta_rule, callback=lambda it, x, r: xs.append(x.copy()))
+    dx = [xs[j + 1] - xs[j] for j in range(len(xs) - 1)]
+    Adx = [op.A(d) for d in dx]
+    worst = 0.0
+    for j in range(len(dx) - 1):
+        num = abs(np.vdot(dx[j + 1], Adx[j]).real)
+        den = np.sqrt(np.vdot(dx[j + 1], Adx[j + 1]).real * np.vdot(dx[j], Adx[j]).real)
+        worst = max(worst, num / den)
+    return worst
+
+
+def test_polak_ribiere_beta_keeps_successive_directions_conjugate():
+    """Pin of the Polak-Ribiere beta (Sec. 3.2).  With r_{j+1} - r_j =
+    -alpha_j A p_j and alpha_j = <r_j, z_j>/<p_j, A p_j>, the PR choice
+    beta = <z_{j+1}, r_{j+1} - r_j>/<z_j, r_j> makes <p_{j+1}, A p_j> vanish
+    exactly for any preconditioner, also an inexact, nonlinear one such as
+    the fixed-k inner CG.  The Fletcher-Reeves beta of Alg. 1 (planted here
+    as the mistake) does not: the k-step preconditioner is not a fixed
+    linear map, so its directions lose conjugacy by O(1e-2)."""
+    dims, sub = (8, 4, 4, 4), (4, 4, 4, 4)
+    op = make(dims, 4, mf=0.05, eps=0.5, seed=21)
+    til = oracle.Tiling(dims, sub)
+    b = W.gaussian_source(dims, op.Ls, 22)
+    pr = _successive_conjugacy(op, til, b, 3, "PR")
+    fr = _successive_conjugacy(op, til, b, 3, "FR")
+    print("successive A-conjugacy: PR", pr, "FR", fr)
+    assert pr < 1e-12
+    assert fr > 1e-5
