@@ -11,7 +11,8 @@ from .dwf import (  # noqa: F401
     GAMMA, GAMMA5, P_PLUS, P_MINUS,
     parity_coords, wilson_hop, build_hop_library,
     ptilde, m5_matrix, mphi_matrix, inverse5, adjoint5, apply5, norm2,
-    MobiusDWF, Tiling, tiling_ok, local_operator, inner_cg, precondition,
+    MobiusDWF, Tiling, tiling_ok, local_operator, padded_operator, truncated_local_operator,
+    inner_cg, precondition,
     pcg, mspcg, cg, SolveInfo, stored, STORAGE_FORMATS,
     transform, transform_dag, local_op_full, reduced_precondition, outer_sum, chi2,
     line_quartic, quartic_min, train_transform,

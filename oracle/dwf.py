@@ -333,15 +333,57 @@ class Tiling:
         return out
 
 
-def local_operator(op: MobiusDWF, tiling: Tiling, vs, subset=None, batch=8):
+def padded_operator(op: MobiusDWF, tiling: Tiling, k):
+    """The padded field of Sec. 3.1.2 for subdomain k, as an operator of its
+    own: a lattice made of the subdomain and a pad of two sites on both sides
+    of every partitioned direction, carrying the original links there, with
+    zero links from the last site of the box in each partitioned direction
+    (so no hop leaves or re-enters the padded box: zero boundary beyond the
+    pad).  Unpartitioned directions keep their periodic links.
+
+    Returns the padded operator and the single-parity indices, in it, of the
+    subdomain's even sites (in the order of ``tiling.index[k]``)."""
+    dims, sub = tiling.dims, tiling.sub
+    part = [s < d for d, s in zip(dims, sub)]
+    nb = [d // s for d, s in zip(dims, sub)]
+    bx = [k % nb[0], (k // nb[0]) % nb[1], (k // (nb[0] * nb[1])) % nb[2], k // (nb[0] * nb[1] * nb[2])]
+    origin = [bx[m] * sub[m] for m in range(4)]
+    L = [sub[m] + 4 if part[m] else dims[m] for m in range(4)]
+    # global coordinate of every local coordinate, per direction
+    g = [(origin[m] - 2 + np.arange(L[m])) % dims[m] if part[m] else np.arange(L[m]) for m in range(4)]
+    Upad = op.U[np.ix_(g[3], g[2], g[1], g[0])].copy()          # [T][Z][Y][X][mu][3][3]
+    for m in range(4):
+        if part[m]:
+            sl = [slice(None)] * 4
+            sl[3 - m] = L[m] - 1                                 # array axes are (t, z, y, x)
+            Upad[tuple(sl) + (m,)] = 0.0
+    pop = MobiusDWF(Upad, op.Ls, op.b, op.c, op.M5, op.mf)
+    cg = parity_coords(dims, 0)[tiling.index[k]]
+    loc = np.stack([(cg[:, m] - origin[m] + 2) if part[m] else cg[:, m] for m in range(4)], axis=1)
+    lex = loc[:, 0] + L[0] * (loc[:, 1] + L[1] * (loc[:, 2] + L[2] * loc[:, 3]))
+    return pop, lex // 2
+
+
+def local_operator(op: MobiusDWF, tiling: Tiling, vs, subset=None, batch=8, padded=False):
     """A_s v_s = R_s A R_s^T v_s for each subdomain (Sec. 2.3, eq. diri: the
     Dirichlet condition is imposed on the whole four-hop operator, so paths
     that leave the subdomain and return -- the snake terms -- are kept).
 
     Each v_s is embedded (zero elsewhere) into its own full even field, the
     full A is applied, and the result is restricted back; ``batch`` fields go
-    through A together."""
+    through A together.  With ``padded`` each A_s is applied on the padded
+    field of its subdomain instead (``padded_operator``, Sec. 3.1.2), which
+    equals R_s A R_s^T on every tiling ``tiling_ok`` accepts and costs the
+    padded box instead of the whole lattice."""
     ids = list(range(tiling.nsub)) if subset is None else list(subset)
+    if padded:
+        out = np.empty_like(vs)
+        for j, k in enumerate(ids):
+            pop, idx = padded_operator(op, tiling, k)
+            full = np.zeros((op.Ls, pop.vh, 4, 3), dtype=np.complex128)
+            full[:, idx] = vs[j]
+            out[j] = pop.A(full)[:, idx]
+        return out
     out = np.empty_like(vs)
     for j0 in range(0, len(ids), batch):
         chunk = ids[j0:j0 + batch]
@@ -354,14 +396,15 @@ def local_operator(op: MobiusDWF, tiling: Tiling, vs, subset=None, batch=8):
     return out
 
 
-def inner_cg(op: MobiusDWF, tiling: Tiling, r, k, subset=None):
+def inner_cg(op: MobiusDWF, tiling: Tiling, r, k, subset=None, padded=False):
     """Preconditioner z = (+)_s CG_k(A_s, r_s) (Sec. 2.4-2.5).
 
     On every subdomain independently: z = 0, res = r_s, p = res,
     rho = <res,res>; repeat k times: q = A_s p, alpha = rho/<p,q>,
     z += alpha p, res -= alpha q, rho' = <res,res>, p = res + (rho'/rho) p.
     No precision-based stop.  A subdomain whose rho or <p,q> is zero keeps
-    its current z.  Returns the restricted solutions [nsub][Ls][n_s][4][3]."""
+    its current z.  Returns the restricted solutions [nsub][Ls][n_s][4][3].
+    ``padded``: A_s through the padded field (see ``local_operator``)."""
     ids = list(range(tiling.nsub)) if subset is None else list(subset)
     rs = np.stack([r[:, tiling.index[j]] for j in ids])
     z = np.zeros_like(rs)
@@ -370,7 +413,7 @@ def inner_cg(op: MobiusDWF, tiling: Tiling, r, k, subset=None):
     rho = np.array([norm2(res[j]) for j in range(len(ids))])
     active = rho > 0.0
     for _ in range(k):
-        q = local_operator(op, tiling, p, subset=ids)
+        q = local_operator(op, tiling, p, subset=ids, padded=padded)
         for j in range(len(ids)):
             if not active[j]:
                 continue
@@ -389,6 +432,38 @@ def inner_cg(op: MobiusDWF, tiling: Tiling, r, k, subset=None):
             p[j] = res[j] + beta * p[j]
             rho[j] = rho_new
     return z
+
+
+def truncated_local_operator(op: MobiusDWF, tiling: Tiling, vs, subset=None):
+    """The operator eq. diri of Sec. 2.3 contrasts with A_s: the Dirichlet
+    cut applied to every hop separately, D_s = 1 - M5^-1 |M^4_eo| M5^-1 |M^4_oe|
+    and D_s^dag likewise, |.| keeping only sites of the subdomain (even and
+    odd) after each hop, and A_trunc = D_s^dag D_s.  It drops the snake terms
+    (paths that leave the subdomain and come back) and so differs from A_s;
+    it is not part of the method and serves only as the comparator that
+    shows an A_s test can see the snake terms."""
+    ids = list(range(tiling.nsub)) if subset is None else list(subset)
+    oc = parity_coords(tiling.dims, 1)
+    nb = [d // s for d, s in zip(tiling.dims, tiling.sub)]
+    bxo = [oc[:, m] // tiling.sub[m] for m in range(4)]
+    label_odd = ((bxo[3] * nb[2] + bxo[2]) * nb[1] + bxo[1]) * nb[0] + bxo[0]
+    out = np.empty_like(vs)
+    for j, k in enumerate(ids):
+        keep = {0: tiling.label == k, 1: label_odd == k}
+
+        def cut(f, par):
+            g = f.copy()
+            g[:, ~keep[par]] = 0
+            return g
+
+        full = np.zeros((op.Ls, op.vh, 4, 3), dtype=np.complex128)
+        full[:, tiling.index[k]] = vs[j]
+        t = apply5(op.M5inv, cut(op.m4(full, 1), 1))
+        d = full - apply5(op.M5inv, cut(op.m4(t, 0), 0))
+        t = apply5(op.M5inv_dag, cut(op.m4_dag(apply5(op.M5inv_dag, d), 1), 1))
+        a = d - cut(op.m4_dag(t, 0), 0)
+        out[j] = a[:, tiling.index[k]]
+    return out
 
 
 def precondition(op, tiling, r, k):
@@ -411,13 +486,16 @@ class SolveInfo:
 
 
 def pcg(op: MobiusDWF, b, tol, maxiter, precond=None, beta_rule="PR", x0=None,
-        callback=None):
+        callback=None, coeffs=None):
     """Preconditioned CG on A x = b (Alg. 1).
 
     alpha = <r,z>/<p,Ap>, x += alpha p, r -= alpha Ap, z = M^-1 r,
     beta = <z_new, r_new - r_old>/<z_old, r_old> (Polak-Ribiere) or
     <z_new, r_new>/<z_old, r_old> (Fletcher-Reeves, as in Alg. 1), p = z + beta p.
-    Stops when ||r|| / ||b|| <= tol.  Without ``precond`` z = r (plain CG)."""
+    Stops when ||r|| / ||b|| <= tol.  Without ``precond`` z = r (plain CG).
+    ``coeffs`` (a list, optional) receives (alpha, beta) of every iteration
+    (beta None on the last one): for plain CG they define the Lanczos
+    tridiagonal matrix of A, whose extreme eigenvalues estimate A's."""
     M = (lambda v: v) if precond is None else precond
     bnorm = np.sqrt(norm2(b))
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -440,6 +518,8 @@ def pcg(op: MobiusDWF, b, tol, maxiter, precond=None, beta_rule="PR", x0=None,
             callback(it, x, r)
         if hist[-1] <= tol:
             converged = True
+            if coeffs is not None:
+                coeffs.append((alpha, None))
             break
         z = M(r)
         rz = np.vdot(z, r).real
@@ -447,6 +527,8 @@ def pcg(op: MobiusDWF, b, tol, maxiter, precond=None, beta_rule="PR", x0=None,
             beta = (rz - np.vdot(z, r_old).real) / rho
         else:
             beta = rz / rho
+        if coeffs is not None:
+            coeffs.append((alpha, beta))
         rho = rz
         p = z + beta * p
     true = np.sqrt(norm2(b - op.A(x))) / bnorm
@@ -459,9 +541,9 @@ def mspcg(op, tiling, b, k, tol, maxiter, x0=None):
                beta_rule="PR", x0=x0)
 
 
-def cg(op, b, tol, maxiter, x0=None):
+def cg(op, b, tol, maxiter, x0=None, coeffs=None):
     """Plain CG (Alg. 1 with M = 1, Fletcher-Reeves beta)."""
-    return pcg(op, b, tol, maxiter, precond=None, beta_rule="FR", x0=x0)
+    return pcg(op, b, tol, maxiter, precond=None, beta_rule="FR", x0=x0, coeffs=coeffs)
 
 
 # --------------------------------------------------------------------------

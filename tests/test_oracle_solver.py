@@ -89,14 +89,29 @@ def padded_local_operator(op, tiling, k, v):
                                       ((8, 8, 4, 2), (4, 4, 4, 2)),
                                       ((8, 8, 8, 8), (4, 4, 4, 4))])
 def test_local_operator_equals_padded_field(dims, sub):
+    """Three constructions of A_s agree: R_s A R_s^T by embedding, the
+    oracle's padded-field operator, and the padded field built here site by
+    site (an independent copy of the Sec. 3.1.2 construction)."""
     op = make(dims, 3, eps=0.7, seed=3)
     til = oracle.Tiling(dims, sub)
     ks = [0, til.nsub - 1]
     vs = rand_field((len(ks), op.Ls, len(til.index[0]), 4, 3))
     As = oracle.local_operator(op, til, vs, subset=ks)
+    Ap = oracle.local_operator(op, til, vs, subset=ks, padded=True)
     for j, k in enumerate(ks):
         ref = padded_local_operator(op, til, k, vs[j])
         assert np.max(np.abs(As[j] - ref)) < 1e-12 * np.max(np.abs(ref))
+        assert np.max(np.abs(Ap[j] - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_padded_inner_cg_equals_embedded_inner_cg():
+    dims, sub = (12, 4, 4, 4), (4, 4, 4, 4)
+    op = make(dims, 4, mf=0.05, seed=4)
+    til = oracle.Tiling(dims, sub)
+    r = rand_field((op.Ls, op.vh, 4, 3))
+    z1 = oracle.inner_cg(op, til, r, 3, subset=[1, 2])
+    z2 = oracle.inner_cg(op, til, r, 3, subset=[1, 2], padded=True)
+    assert np.max(np.abs(z1 - z2)) < 1e-12 * np.max(np.abs(z1))
 
 
 def test_snake_terms_matter():
@@ -137,6 +152,15 @@ def test_snake_terms_matter():
     a_s = oracle.local_operator(op, til, v[None], subset=[k])[0]
     rel = np.linalg.norm(a_s - a_trunc) / np.linalg.norm(a_s)
     assert rel > 1e-3
+    # the oracle's per-hop truncated operator (the comparator of the GPU
+    # tests) is this construction
+    a_or = oracle.truncated_local_operator(op, til, v[None], subset=[k])[0]
+    assert np.max(np.abs(a_or - a_trunc)) < 1e-13 * np.max(np.abs(a_trunc))
+    # and reduces to A when the subdomain is the whole lattice
+    til1 = oracle.Tiling(dims, dims)
+    w = rand_field((op.Ls, op.vh, 4, 3))
+    a1 = oracle.truncated_local_operator(op, til1, w[:, til1.index[0]][None], subset=[0])[0]
+    assert np.max(np.abs(a1 - op.A(w)[:, til1.index[0]])) < 1e-12 * np.max(np.abs(a1))
 
 
 def test_local_operator_hpd():
