@@ -2,11 +2,17 @@
 
 A step is one complete solve A x = b (A = D^dag D of the even-odd Mobius
 domain-wall operator) to a true relative residual of 1e-10, with the source
-and gauge field already resident in HBM.  The default workload is the single
-mixed-precision solve: 16^3x32 lattice, Ls = 12, mf = 0.01, links
-exp(i 0.5 H); outer PCG in FP32 with FP64 reliable updates, inner CG in FP16
-storage (FP32 arithmetic) on 256 subdomains of 4^3x8, 6 inner iterations.
-Plain CG (FP32 + FP64 reliable updates, and FP64) is timed beside it.
+and gauge field already resident in HBM.  The default workload is one GPU's
+share at production shape: a 32^3x64 lattice, Ls = 12, mf = 0.00078, links
+exp(i 0.6 H); outer PCG in FP32 with FP64 reliable updates, inner CG in FP16
+storage (FP32 arithmetic, MFMA fifth-dimension products) on 256 subdomains
+of 8^3x16 with the snake terms kept.  Plain CG (FP32 + FP64 reliable
+updates, and FP64) is timed beside it on the same GPU.
+
+The legs after the timed steps (plain CG baselines, the serving sample, the
+CPU oracle baseline) run only while the whole run stays inside --budget-s,
+so that a long step count never pushes the run past its time limit; a
+skipped leg says so in the JSON line.
 
 Prints one JSON line.  `value` is the MSPCG time-to-solution in seconds.
 """
@@ -54,13 +60,12 @@ def stage_bytes(cfg, inner_prec):
     """Algorithmic bytes of one launch of each hop stage: every input site
     read once, every output written once, the epilogue's second field (w) and,
     in the last hop, the field of the fused <p, A p> partial read once where
-    they are nonzero, and the links the launch needs read once each (FP32 for
-    the outer hops, FP16 for the subdomain hops of the 16- and 8-bit formats):
-    the 8 links of each output 4D site (shared over Ls), at most every link of
-    the lattice (subdomain regions overlap their neighbours, so the links of one
-    launch of a subdomain hop repeat across subdomains).  Keys: profiling
-    kinds of the library (21..24 outer FP32 hops of A, 11..14 subdomain hops
-    h1..h4)."""
+    they are nonzero, and the 8 links of each output 4D site once (shared
+    over Ls; FP32 for the outer hops, FP16 for the subdomain hops of the 16-
+    and 8-bit formats).  Subdomain regions overlap their neighbours, so a
+    subdomain hop counts a link once for every output site that needs it,
+    whichever subdomain the site belongs to.  Keys: profiling kinds of the
+    library (21..24 outer FP32 hops of A, 11..14 subdomain hops h1..h4)."""
     X, Y, Z, T = cfg.dims
     vh = X * Y * Z * T // 2
     Ls = cfg.Ls
@@ -74,9 +79,8 @@ def stage_bytes(cfg, inner_prec):
            23: 2 * sp32 * n5 + link * vh, 24: 4 * sp32 * n5 + link * vh}
     nC, nN1, nN2 = region_counts(cfg.sub, cfg.dims)
     ns = cfg.n_subdomains
-    all_links = 2 * vh * 4 * link_in // 8
     for k, (sin, sout) in {11: (nC, nN1), 12: (nN1 + nC, nN2), 13: (nN2, nN1), 14: (nN1 + 2 * nC, nC)}.items():
-        out[k] = ns * Ls * sp16 * (sin + sout) + min(ns * link_in * sout, all_links)
+        out[k] = ns * Ls * sp16 * (sin + sout) + ns * link_in * sout
     return out, (nC, nN1, nN2)
 
 
@@ -398,7 +402,8 @@ def kernels_bench(args):
 
 
 KERNEL_SOURCES = ["common.h", "sitekern.h", "kernels.h", "kernels.hip", "sub.hip"]
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hop_kernels_c2_hbm_traffic.md")
+def traffic_summary(workload):
+    return os.path.join(ROOT, "profiles", f"hop_kernels_{workload}_hbm_traffic.md")
 PROF_STRIDE = 8   # hop launches per timed launch in the bench's timed region
 
 
@@ -416,7 +421,7 @@ def measured_traffic(workload, stage):
     counter summary (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain
     copy); None when the kernels changed since, or for another workload."""
     try:
-        txt = open(TRAFFIC_SUMMARY).read()
+        txt = open(traffic_summary(workload)).read()
         blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
@@ -426,12 +431,15 @@ def measured_traffic(workload, stage):
     return None if k is None else k["traffic_bytes"]
 
 
+T_BEGIN = time.time()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4")
     ap.add_argument("--inner-prec", default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -442,13 +450,16 @@ def main():
                     help="also scan the reduced operator with b + c scaled by Ls / Lhat")
     ap.add_argument("--log-every", type=int, default=0, help="solver progress line every N outer iterations")
     ap.add_argument("--no-cg64", action="store_true", help="skip the FP64 CG baseline")
-    ap.add_argument("--no-prec-compare", action="store_true",
-                    help="skip the MSPCG solves with the other inner storage formats")
+    ap.add_argument("--prec-compare", action="store_true",
+                    help="also solve with the other inner storage formats (outside the timed region)")
+    ap.add_argument("--budget-s", type=float, default=550.0,
+                    help="wall-clock budget of the whole run: legs after the timed steps are skipped "
+                         "when they would not fit")
     ap.add_argument("--oracle-check", action="store_true",
                     help="relative residual of the MSPCG solution by the FP64 oracle on the host")
     ap.add_argument("--requests", type=int, default=None, help="serving stream length")
     ap.add_argument("--budget-gb", type=int, default=200, help="HBM budget of the request server (GB)")
-    ap.add_argument("--serve-sample", type=int, default=12,
+    ap.add_argument("--serve-sample", type=int, default=10,
                     help="requests of the serving sample in solve mode (0: none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -529,26 +540,42 @@ def main():
     assert all(st.status == 0 and st.true_rel_resid <= cfg.tol for st in sts), "MSPCG did not converge"
     x_ms = xt.clone()
 
+    # legs after the timed region run while the run stays inside the budget
+    t_solve = statistics.median(times)
+    skipped = []
+
+    def fits(name, est_s):
+        ok = time.time() - T_BEGIN + est_s <= args.budget_s
+        if not ok:
+            skipped.append(name)
+            log(f"[bench] {name}: skipped (estimated {est_s:.0f}s would exceed the {args.budget_s:.0f}s budget)")
+        return ok
+
     # baselines on the same GPU (outside the timed region)
-    cg32 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp32", reliable_delta=0.1,
-               beta_rule="FR", use_precond=False)
-    log(f"[bench] CG fp32: {cg32[-1][0]:.3f}s, {cg32[-1][1].outer_iters} iters, "
-        f"true resid {cg32[-1][1].true_rel_resid:.2e}")
-    if args.no_cg64:
-        cg64 = cg32
-    else:
+    cg32 = cg64 = None
+    x_cg = None
+    if fits("cg_fp32", 0.6 * t_solve * args.cg_steps):
+        cg32 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp32", reliable_delta=0.1,
+                   beta_rule="FR", use_precond=False)
+        log(f"[bench] CG fp32: {cg32[-1][0]:.3f}s, {cg32[-1][1].outer_iters} iters, "
+            f"true resid {cg32[-1][1].true_rel_resid:.2e}")
+        x_cg = xt.clone()
+    if not args.no_cg64 and fits("cg_fp64", 1.5 * t_solve * args.cg_steps):
         cg64 = run(args.cg_steps, tol=cfg.tol, maxiter=100000, outer_prec="fp64", reliable_delta=0.1,
                    beta_rule="FR", use_precond=False)
         log(f"[bench] CG fp64: {cg64[-1][0]:.3f}s, {cg64[-1][1].outer_iters} iters, "
             f"true resid {cg64[-1][1].true_rel_resid:.2e}")
-    x_cg = xt.clone()
-    sol_rel = float(torch.linalg.vector_norm(x_ms - x_cg) / torch.linalg.vector_norm(x_cg))
+        x_cg = xt.clone()
+    sol_rel = (float(torch.linalg.vector_norm(x_ms - x_cg) / torch.linalg.vector_norm(x_cg))
+               if x_cg is not None else None)
 
     # the preconditioner's storage format against the outer iteration count
     # (Sec. 3.2: 8-bit storage is cheaper per inner step, 16-bit a better
     # preconditioner); one solve each, outside the timed region
     storage = {}
-    for p in ([] if args.no_prec_compare else [q for q in ("fp16", "bf16", "int8") if q != inner]):
+    for p in ([q for q in ("fp16", "bf16", "int8") if q != inner] if args.prec_compare else []):
+        if not fits(f"inner_{p}", 1.3 * t_solve):
+            continue
         (dt, st), = run(1, **dict(mspcg_params, inner_prec=p))
         storage[p] = {"time_s": dt, "outer_iters": st.outer_iters, "status": st.status,
                       "true_rel_resid": st.true_rel_resid}
@@ -611,13 +638,14 @@ def main():
                   "inner_iters_total": sts[-1].inner_iters_total, "reliable_updates": sts[-1].reliable_updates,
                   "true_rel_resid": sts[-1].true_rel_resid,
                   "precond_ms_per_solve": ms_pc / args.steps},
-        "cg_fp32": {"time_s": cg32[-1][0], "outer_iters": cg32[-1][1].outer_iters,
-                    "true_rel_resid": cg32[-1][1].true_rel_resid},
-        "cg_fp64": None if args.no_cg64 else {"time_s": cg64[-1][0], "outer_iters": cg64[-1][1].outer_iters,
+        "cg_fp32": None if cg32 is None else {"time_s": cg32[-1][0], "outer_iters": cg32[-1][1].outer_iters,
+                                              "true_rel_resid": cg32[-1][1].true_rel_resid},
+        "cg_fp64": None if cg64 is None else {"time_s": cg64[-1][0], "outer_iters": cg64[-1][1].outer_iters,
                                               "true_rel_resid": cg64[-1][1].true_rel_resid},
         "inner_storage": storage,
-        "speedup_vs_cg_fp32": cg32[-1][0] / statistics.median(times),
-        ("solution_rel_diff_mspcg_vs_cg32" if args.no_cg64 else "solution_rel_diff_mspcg_vs_cg64"): sol_rel,
+        "speedup_vs_cg_fp32": None if cg32 is None else cg32[-1][0] / statistics.median(times),
+        "speedup_vs_cg_fp64": None if cg64 is None else cg64[-1][0] / statistics.median(times),
+        ("solution_rel_diff_mspcg_vs_cg64" if cg64 is not None else "solution_rel_diff_mspcg_vs_cg32"): sol_rel,
         "kernels": kernels,
         "dslash": {"outer_hop_GBps": gbs_out, "outer_hop_avg_ms": avg_out, "outer_launches_timed": n_out,
                    "inner_hop_GBps": gbs_in, "inner_hop_avg_ms": avg_in, "inner_launches_timed": n_in,
@@ -638,7 +666,10 @@ def main():
         res = float(np.linalg.norm(r) / np.linalg.norm(b))
         log(f"[bench] oracle residual {res:.3e} ({time.perf_counter() - t:.1f}s)")
         line["mspcg"]["oracle_rel_resid"] = res
-    if args.serve_sample > 0:
+    if not args.no_cpu_baseline and fits("cpu_baseline", 45.0):
+        line["cpu_baseline"] = cpu_baseline(cfg, U, b, sts[-1].outer_iters,
+                                            None if cg32 is None else cg32[-1][1].outer_iters)
+    if args.serve_sample > 0 and fits("serving_sample", 45.0):
         del s
         r = serve_stream(nreq=args.serve_sample, **SERVE_SAMPLE)
         line["p50_p99"] = {"p50_s": r["p50_s"], "p99_s": r["p99_s"], "solves_per_s": r["solves_per_s"],
@@ -647,34 +678,65 @@ def main():
                                      % (r["requests"], r["load"]),
                            "detail": r}
 
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, U, b, sts[-1].outer_iters, cg32[-1][1].outer_iters)
+    line["skipped_for_time"] = skipped
+    line["run_s"] = time.time() - T_BEGIN
     print(json.dumps(line), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(cfg, U, b, mspcg_iters, cg_iters):
     """The FP64 oracle on the host cores, on a bounded sample of the same
-    solve, scaled to a time-to-solution."""
+    solve, scaled to a time-to-solution: one application of the full A and
+    the k-step inner CG of one subdomain (its A_s through the padded field,
+    Sec. 3.1.2), with all threads and again with one thread."""
     os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+    from threadpoolctl import threadpool_info, threadpool_limits
     import oracle
     op = oracle.MobiusDWF(U, cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
     til = oracle.Tiling(cfg.dims, cfg.sub)
     t = time.perf_counter()
-    q = op.A(b)
+    op.A(b)
     t_A = time.perf_counter() - t
     log(f"[bench] oracle: A in {t_A:.2f}s")
-    nsample = 1
     t = time.perf_counter()
-    oracle.inner_cg(op, til, b, cfg.inner_iters, subset=[0])
+    oracle.inner_cg(op, til, b, cfg.inner_iters, subset=[0], padded=True)
     t_pc1 = time.perf_counter() - t
-    log(f"[bench] oracle: inner CG (k={cfg.inner_iters}) on {nsample} subdomain in {t_pc1:.2f}s")
-    per_iter_ms = t_A + t_pc1 * til.nsub / nsample
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": per_iter_ms * mspcg_iters, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"one oracle A application ({t_A:.2f}s) and the inner CG on {nsample} of {til.nsub} "
-                       f"subdomains ({t_pc1:.2f}s), extrapolated to {til.nsub} subdomains and the GPU's "
-                       f"{mspcg_iters} outer iterations"),
-            "cg_fp64_extrapolated_s": t_A * cg_iters}
+    log(f"[bench] oracle: inner CG (k={cfg.inner_iters}) on 1 subdomain in {t_pc1:.2f}s")
+    pools = threadpool_info()
+    threads = max([p.get("num_threads", 1) for p in pools] + [1])
+    # one A_s application of the same subdomain, with all threads and with one
+    vs = til.restrict(b)[:1]
+    t = time.perf_counter()
+    oracle.local_operator(op, til, vs, subset=[0], padded=True)
+    t_as = time.perf_counter() - t
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        oracle.local_operator(op, til, vs, subset=[0], padded=True)
+        t_as_1 = time.perf_counter() - t
+    log(f"[bench] oracle: one A_s application {t_as:.3f}s, on 1 thread {t_as_1:.3f}s")
+    per_iter = t_A + t_pc1 * til.nsub
+    out = {"value": per_iter * mspcg_iters, "unit": "s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+           "sample": (f"one oracle A application ({t_A:.2f}s) and the k={cfg.inner_iters} inner CG of 1 of "
+                      f"{til.nsub} subdomains through its padded field ({t_pc1:.2f}s), {threads} threads; "
+                      f"extrapolated to {til.nsub} subdomains and the GPU's {mspcg_iters} outer iterations"),
+           "one_thread": {"A_s_one_subdomain_s": t_as_1, "A_s_one_subdomain_all_threads_s": t_as,
+                          "threads_speedup": t_as_1 / t_as,
+                          "value_extrapolated_s": per_iter * (t_as_1 / t_as) * mspcg_iters,
+                          "sample": "one A_s application through the padded field on 1 thread against all "
+                                    "threads; the whole solve scaled by that ratio"}}
+    if cg_iters is not None:
+        out["cg_fp64_extrapolated_s"] = t_A * cg_iters
+    return out
 
 
 if __name__ == "__main__":

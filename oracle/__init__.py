@@ -12,6 +12,7 @@ from .dwf import (  # noqa: F401
     parity_coords, wilson_hop, build_hop_library,
     ptilde, m5_matrix, mphi_matrix, inverse5, adjoint5, apply5, norm2,
     MobiusDWF, Tiling, tiling_ok, local_operator, padded_operator, truncated_local_operator,
+    local_operator_stored, inner_cg_stored, stored_links,
     inner_cg, precondition,
     pcg, mspcg, cg, SolveInfo, stored, STORAGE_FORMATS,
     transform, transform_dag, local_op_full, reduced_precondition, outer_sum, chi2,

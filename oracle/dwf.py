@@ -466,6 +466,93 @@ def truncated_local_operator(op: MobiusDWF, tiling: Tiling, vs, subset=None):
     return out
 
 
+def local_operator_stored(op: MobiusDWF, tiling: Tiling, vs, fmt, subset=None):
+    """A_s v_s evaluated as the fused kernels of eq. detail (Sec. 3.1.3) on
+    the padded field of each subdomain (Sec. 3.1.2), with every kernel's
+    output field stored in ``fmt`` and read back (Sec. 3.2: the
+    preconditioner's kernels load fixed-point fields, compute in single
+    precision and store their output in the fixed-point format).  The input
+    is stored first; then, with p the stored input,
+
+        t0 = M_phi p                                    (kernel M_phi)
+        a  = M_phi M5^-1 D^w t0                         (kernel M_phi M5^-1 D^w)
+        c  = M5^-dag (p - M5^-1 D^w a)  = M5^-dag D p   (kernel M5^-dag M5^-1 D^w
+                                                         with the 1 - ... of D)
+        e  = M5^-dag M_phi^dag D^w^dag c                (kernel M5^-dag M_phi^dag D^w^dag)
+        q  = M5^dag c - M_phi^dag D^w^dag e = D^dag D p (kernel M_phi^dag D^w^dag
+                                                         with the 1 - ... of D^dag)
+
+    each output stored.  How the two 1 - ... terms join the kernels is a
+    reading (the paper skips them); with ``fmt = 'fp64'`` the chain is A_s
+    exactly.  The fifth-dimension operators are applied one after another,
+    each in FP64."""
+    ids = list(range(tiling.nsub)) if subset is None else list(subset)
+    S = lambda f: stored(f, fmt)   # noqa: E731
+    out = np.empty_like(vs)
+    for j, k in enumerate(ids):
+        pop, idx = padded_operator(op, tiling, k)
+        p = np.zeros((op.Ls, pop.vh, 4, 3), dtype=np.complex128)
+        p[:, idx] = vs[j]
+        p = S(p)
+        t0 = S(apply5(pop.Mphi, p))
+        a = S(apply5(pop.Mphi, apply5(pop.M5inv, wilson_hop(pop.U, t0, 1))))
+        c = S(apply5(pop.M5inv_dag, p - apply5(pop.M5inv, wilson_hop(pop.U, a, 0))))
+        e = S(apply5(pop.M5inv_dag, apply5(pop.Mphi_dag, wilson_hop(pop.U, c, 1, dagger=True))))
+        q = S(apply5(adjoint5(pop.M5op), c) - apply5(pop.Mphi_dag, wilson_hop(pop.U, e, 0, dagger=True)))
+        out[j] = q[:, idx]
+    return out
+
+
+def inner_cg_stored(op: MobiusDWF, tiling: Tiling, r, k, fmt, subset=None):
+    """The k-step inner CG of ``inner_cg`` with the preconditioner's fields in
+    ``fmt`` (Sec. 3.2: the inner CG's matrix multiplications and BLAS
+    operations use the fixed-point formats): r_s is stored on entry, every
+    vector an iteration produces (z, the residual, the search direction) is
+    stored after its update, and q = A_s p comes from
+    ``local_operator_stored``; the scalars are FP64 and computed from the
+    stored vectors.  With ``fmt = 'fp64'`` it is ``inner_cg``."""
+    ids = list(range(tiling.nsub)) if subset is None else list(subset)
+    S = lambda f: stored(f, fmt)   # noqa: E731
+    rs = S(np.stack([r[:, tiling.index[j]] for j in ids]))
+    z = np.zeros_like(rs)
+    res = rs.copy()
+    p = res.copy()
+    rho = np.array([norm2(res[j]) for j in range(len(ids))])
+    active = rho > 0.0
+    for _ in range(k):
+        q = local_operator_stored(op, tiling, p, fmt, subset=ids)
+        for j in range(len(ids)):
+            if not active[j]:
+                continue
+            pq = np.vdot(p[j], q[j]).real
+            if pq == 0.0:
+                active[j] = False
+                continue
+            alpha = rho[j] / pq
+            z[j] = S(z[j] + alpha * p[j])
+            res[j] = S(res[j] - alpha * q[j])
+            rho_new = norm2(res[j])
+            if rho_new == 0.0:
+                active[j] = False
+                continue
+            beta = rho_new / rho[j]
+            p[j] = S(res[j] + beta * p[j])
+            rho[j] = rho_new
+    return z
+
+
+def stored_links(U, fmt):
+    """Links as the preconditioner's kernels hold them: for the 16- and 8-bit
+    field formats every real and imaginary part rounded to the nearest FP16
+    value (ties to even; a reading: the paper's low-precision kernels keep
+    their links in 16 bits), for ``fp32`` to FP32, for ``fp64`` unchanged."""
+    U = np.asarray(U, dtype=np.complex128)
+    if fmt == "fp64":
+        return U.copy()
+    t = np.float32 if fmt == "fp32" else np.float16
+    return U.real.astype(t).astype(np.float64) + 1j * U.imag.astype(t).astype(np.float64)
+
+
 def precondition(op, tiling, r, k):
     """z = M^-1 r with M = (+)_s A_s approximated by k inner CG steps."""
     zs = inner_cg(op, tiling, r, k)

@@ -117,3 +117,95 @@ def test_gaussian_error_matches_uniform_rounding_model():
     assert abs(e / model - 1) < 0.03, (e, model)
     assert np.array_equal(oracle.stored(psi, "fp32"), psi.astype(np.complex64).astype(np.complex128))
     assert np.array_equal(oracle.stored(psi, "fp64"), psi)
+
+
+# ---------------------------------------------------------------- storage points of the preconditioner
+
+import workloads as W  # noqa: E402
+
+
+def _case(dims=(8, 4, 4, 4), Ls=4, sub=(4, 4, 4, 4), seed=9):
+    U = W.gauge_field(dims, 0.5, 11)
+    op = oracle.MobiusDWF(U, Ls, 1.5, 0.5, 1.8, 0.1)
+    til = oracle.Tiling(dims, sub)
+    g = np.random.default_rng(seed).standard_normal((Ls, op.vh, 4, 3, 2))
+    return U, op, til, g[..., 0] + 1j * g[..., 1]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("dims,Ls,sub", [((8, 4, 4, 4), 4, (4, 4, 4, 4)), ((8, 8, 4, 2), 6, (4, 4, 4, 2))])
+def test_fused_kernel_chain_is_the_local_operator(dims, Ls, sub):
+    """The eq.-detail chain of fused kernels on the padded field, stored in
+    FP64 (no rounding), equals A_s = R_s A R_s^T built by embedding into the
+    whole lattice (pinned independently): a wrong grouping of the fifth-
+    dimension operators, a dropped 1 - ... term or a wrong parity fails."""
+    U, op, til, r = _case(dims, Ls, sub)
+    vs = til.restrict(r)
+    assert _rel(oracle.local_operator_stored(op, til, vs, "fp64"), oracle.local_operator(op, til, vs)) < 1e-14
+
+
+def test_fused_kernel_chain_stores_every_kernel_output(monkeypatch):
+    """Six storage points per subdomain: the input and the outputs of the five
+    kernels (M_phi, M_phi M5^-1 D^w, M5^-dag M5^-1 D^w, M5^-dag M_phi^dag
+    D^w^dag, M_phi^dag D^w^dag); each is a field of the padded box."""
+    import oracle.dwf as D
+    U, op, til, r = _case()
+    vs = til.restrict(r)[:1]
+    calls = []
+    real = D.stored
+
+    def spy(f, fmt):
+        calls.append(f.shape)
+        return real(f, fmt)
+
+    monkeypatch.setattr(D, "stored", spy)
+    D.local_operator_stored(op, til, vs, "fp16", subset=[0])
+    pop, _ = oracle.padded_operator(op, til, 0)
+    assert calls == [(op.Ls, pop.vh, 4, 3)] * 6
+
+
+def test_stored_chain_error_follows_the_formats():
+    """Against exact A_s the stored chain errs by a few roundings of its
+    format: FP32 ~1e-7, FP16 (2^-11 relative steps) ~3e-4, BF16 (2^-8)
+    ~2.5e-3, int8 (steps of m/127) ~1e-2, in that order, each within a
+    factor of the one-store error of the input times the six stores."""
+    U, op, til, r = _case()
+    vs = til.restrict(r)
+    ex = oracle.local_operator(op, til, vs)
+    errs = {}
+    for fmt in ("fp32", "fp16", "bf16", "int8"):
+        one = _rel(oracle.stored(vs, fmt), vs)               # one store of the input
+        e = _rel(oracle.local_operator_stored(op, til, vs, fmt), ex)
+        assert 0.3 * one < e < 6 * one, (fmt, e, one)
+        errs[fmt] = e
+    assert errs["fp32"] < errs["fp16"] < errs["bf16"] < errs["int8"]
+
+
+def test_stored_inner_cg():
+    """In FP64 the stored inner CG is the inner CG; in the 16- and 8-bit
+    formats it departs from it by the order of its format's rounding."""
+    U, op, til, r = _case()
+    z = oracle.inner_cg(op, til, r, 3)
+    assert _rel(oracle.inner_cg_stored(op, til, r, 3, "fp64"), z) < 1e-14
+    for fmt, lo, hi in (("fp16", 1e-4, 2e-3), ("bf16", 1e-3, 1e-2), ("int8", 3e-3, 4e-2)):
+        e = _rel(oracle.inner_cg_stored(op, til, r, 3, fmt), z)
+        assert lo < e < hi, (fmt, e)
+
+
+def test_stored_links():
+    """FP16 links: every real and imaginary part on the FP16 grid, within half
+    an FP16 ulp of the FP64 value (values already on the grid unchanged);
+    FP64 unchanged."""
+    U = W.gauge_field((4, 4, 4, 4), 0.5, 5)
+    L = oracle.stored_links(U, "fp16")
+    for part in (L.real, L.imag):
+        assert np.array_equal(part.astype(np.float16).astype(np.float64), part)
+    x = np.concatenate([U.real.ravel(), U.imag.ravel()])
+    y = np.concatenate([L.real.ravel(), L.imag.ravel()])
+    nz = np.abs(x) > 2.0 ** -14
+    assert np.all(np.abs(y - x)[nz] <= 2.0 ** -11 * np.abs(x)[nz] * (1 + 1e-12))
+    assert np.array_equal(oracle.stored_links(L, "fp16"), L)
+    assert np.array_equal(oracle.stored_links(U, "fp64"), U)
