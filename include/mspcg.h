@@ -256,6 +256,24 @@ mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* i
 mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
                                 void* hip_stream);
 
+/* As mspcg_apply_device, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the call makes no hipMalloc, hipFree or other allocation.
+ * Every workspace of the operator (the converted input and output, scratch
+ * fields, subdomain region fields, partial sums) is carved from a static
+ * device array of 128 MiB that the library holds on each device it runs on
+ * until the process ends.  The caller still passes the device FP64 input
+ * and output.  All calls on one device share that array and it keeps the
+ * last call's contents: calls that overlap in time on one device (on any
+ * streams or handles) race and must be serialised by the caller.  The
+ * handle must have its gauge field and Mobius parameters set (those calls
+ * allocate the handle's own state); profiling is not done inside this call.
+ * Errors: as mspcg_apply_device; INVALID_ARG also when the operator's
+ * workspace exceeds the static array (e.g. an FP32 A needs about 5 fields of
+ * 96 Ls V/2 bytes) or for PRECOND with a reduced-Ls preconditioner set. */
+mspcg_status mspcg_apply_device_noalloc(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
+                                        void* hip_stream);
+
 /* Kernel timing.  With profiling on, the library brackets every launch of its
  * hop kernels with HIP events on the stream they run on; mspcg_get_kernel_time
  * returns the number of timed launches and their summed duration in ms for a

@@ -120,6 +120,7 @@ _SIGS = {
     "mspcg_get_tchunk": [_h, _i32, _i32, ctypes.POINTER(_i32)],
     "mspcg_apply": [_h, _i32, ctypes.c_int, _p, _p],
     "mspcg_apply_device": [_h, _i32, ctypes.c_int, _p, _p, _p],
+    "mspcg_apply_device_noalloc": [_h, _i32, ctypes.c_int, _p, _p, _p],
     "mspcg_set_profiling": [_h, _i32],
     "mspcg_get_kernel_time": [_h, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_d)],
 }
@@ -353,6 +354,10 @@ class MSPCG:
     def apply_device(self, op, prec, in_ptr, out_ptr, stream=None):
         _check(mspcg_apply_device(self._h, OPS[op] if isinstance(op, str) else int(op),
                                   PREC[prec] if isinstance(prec, str) else int(prec), in_ptr, out_ptr, stream))
+
+    def apply_device_noalloc(self, op, prec, in_ptr, out_ptr, stream=None):
+        _check(mspcg_apply_device_noalloc(self._h, OPS[op] if isinstance(op, str) else int(op),
+                                          PREC[prec] if isinstance(prec, str) else int(prec), in_ptr, out_ptr, stream))
 
     def set_profiling(self, on=True, stride=1):
         """HIP-event timing of the hop stages; stride N > 1 times one launch in N of each stage."""

@@ -10,6 +10,12 @@ namespace mspcg {
 
 enum class Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, I8 = 4 };
 
+// Size of the static device workspace of mspcg_apply_device_noalloc (one
+// copy per device, held until the process ends), and its address on the
+// current device (resolved once per device; call with the device current).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+void* scratch_device_ptr();
+
 // A single-parity 5D field in device memory, type-erased.
 struct FieldPtr {
   void* data = nullptr;

@@ -2,6 +2,8 @@
 // fifth-dimension-only operator, layout conversions, the outer solver's
 // BLAS-1 and deterministic reductions.
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -22,6 +24,32 @@ namespace mspcg {
 static std::atomic<int> g_mfma_epilogue{1};
 void set_mfma_epilogue(bool on) { g_mfma_epilogue.store(on ? 1 : 0); }
 bool mfma_epilogue() { return g_mfma_epilogue.load() != 0; }
+
+// ---------------------------------------------------------------- static workspace
+// Device memory for the entry point that allocates nothing
+// (mspcg_apply_device_noalloc): every workspace that call needs is carved
+// from this array.  Each device that loads the library holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is a stand-in, not a device address):
+// scratch_device_ptr resolves the address on each device once and the
+// library uses only that pointer.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void* scratch_device_ptr() {
+  static std::mutex mu;
+  static std::map<int, void*> ptr;   // device -> address of its copy
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("scratch: hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptr.find(dev);
+  if (it != ptr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    throw std::runtime_error(std::string("scratch: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+  ptr[dev] = p;
+  return p;
+}
 
 bool uses_mfma(int Ls, Prec p) { return p != Prec::F64 && Ls <= 16 && mfma_epilogue(); }
 

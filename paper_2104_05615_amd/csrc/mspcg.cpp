@@ -60,11 +60,13 @@ thread_local bool tl_capturing = false;
 struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
+  bool owned = true;   // false: a view into the static workspace (never freed)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   void ensure(size_t bytes) {
     if (bytes <= n && p) return;
+    if (!owned) throw Error(MSPCG_ERR_HIP, "workspace view cannot grow");
     if (tl_capturing) throw Error(MSPCG_ERR_HIP, "workspace growth during graph capture");
     std::unique_lock<std::shared_mutex> lk(g_capture_gate);
     free_locked();
@@ -73,11 +75,16 @@ struct DevBuf {
   }
   void release() {
     if (!p) return;
+    if (!owned) {   // a view: nothing to free
+      p = nullptr;
+      n = 0;
+      return;
+    }
     std::unique_lock<std::shared_mutex> lk(g_capture_gate);
     free_locked();
   }
   void free_locked() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     n = 0;
   }
@@ -384,6 +391,15 @@ struct mspcg_ctx {
   bool have_solver = false;
 
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
+  // Static-workspace mode (mspcg_apply_device_noalloc): while `arena` is set,
+  // buf() hands out views of the device's static workspace, bump-allocated
+  // per call, instead of growing the handle's own buffers.
+  void* scratch = nullptr;   // this device's static workspace (resolved in ensure_hip)
+  struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, off = 0;
+  } arena;
+  std::map<std::string, std::unique_ptr<DevBuf>> arena_ws;
   double* h_scal = nullptr;   // pinned
   int* h_flag = nullptr;      // pinned: RHS still active, one slot per graph replay in flight
   // pinned bounce buffer: every transfer between host memory the caller owns
@@ -447,6 +463,7 @@ struct mspcg_ctx {
     HIPCHK(hipHostMalloc((void**)&h_scal, SLOT_COUNT * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h_flag, 4 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&h_bounce, kBounce, hipHostMallocDefault));
+    scratch = scratch_device_ptr();   // device current: its copy of the static workspace
     hip_ready = true;
   }
 
@@ -472,6 +489,20 @@ struct mspcg_ctx {
   }
 
   DevBuf& buf(const std::string& key, size_t bytes) {
+    if (arena.base) {
+      auto& v = arena_ws[key];
+      if (!v) v.reset(new DevBuf());
+      v->owned = false;
+      if (v->p && v->n >= bytes) return *v;
+      const size_t off = (arena.off + 255) & ~size_t(255);
+      if (off > arena.cap || bytes > arena.cap - off)
+        throw Error(MSPCG_ERR_INVALID_ARG, "workspace of this call exceeds the static workspace (" +
+                                               std::to_string(arena.cap >> 20) + " MiB)");
+      v->p = arena.base + off;
+      v->n = bytes;
+      arena.off = off + bytes;
+      return *v;
+    }
     auto& p = ws[key];
     if (!p) p.reset(new DevBuf());
     p->ensure(bytes);
@@ -2184,6 +2215,38 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
     h->ensure_hip();
+    apply_impl(h, op, P, in, out, hip_stream ? (hipStream_t)hip_stream : h->stream);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_apply_device_noalloc(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
+                                        void* hip_stream) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
+    const Prec P = to_prec(prec);
+    need_state(h);
+    if (!h->hip_ready || !h->scratch) throw Error(MSPCG_ERR_NO_GAUGE, "handle not initialised on its device");
+    if (op == MSPCG_OP_PRECOND && h->Lh > 0)
+      throw Error(MSPCG_ERR_INVALID_ARG, "the reduced-Ls preconditioner is not available without allocation");
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
+    check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
+    HIPCHK(hipSetDevice(h->device));
+    struct Restore {   // leave the handle as it was, also on an error
+      mspcg_ctx* h;
+      bool prof;
+      ~Restore() {
+        h->arena = mspcg_ctx::Arena();
+        h->arena_ws.clear();
+        h->profiling = prof;
+      }
+    } restore{h, h->profiling};
+    h->profiling = false;   // no event creation inside this call
+    h->arena_ws.clear();
+    h->arena.base = static_cast<char*>(h->scratch);
+    h->arena.cap = kScratchBytes;
+    h->arena.off = 0;
     apply_impl(h, op, P, in, out, hip_stream ? (hipStream_t)hip_stream : h->stream);
     return MSPCG_OK;
   });
