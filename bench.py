@@ -109,28 +109,34 @@ SERVE_FULL = dict(volumes=list(SERVE_VOLUMES), masses=[0.1, 0.01, 0.001], max_rh
 SERVE_SAMPLE = dict(volumes=["8^4x8", "16^3x32x12"], masses=[0.1, 0.01], max_rhs=3)
 
 
-def serve_stream(volumes, masses, max_rhs, nreq, seed=105, load=0.75, budget_gb=200, max_inflight=4,
-                 inner_iters=6):
+def serve_stream(volumes, masses, max_rhs, nreq=None, seed=105, load=0.75, budget_gb=200, max_inflight=4,
+                 inner_iters=6, mode="batching", slots=8, work_s=None, svc=None):
     """Poisson stream of batched solves through the library's request server.
 
     Requests draw a volume, a mass and 1..max_rhs Gaussian sources (seeded,
     generated on the device); the gauge fields (one per volume, links
     exp(i 0.5 H), seeds 105, 106, ...) are resident.  The service time of each
-    (volume, mass) is measured once, alone, with one RHS; the arrival rate is
-    `load` times the capacity those times imply for serving the drawn
-    requests one after another.  Latency is submit -> completion, measured by
-    the server."""
+    (volume, mass) is measured once, alone, with one RHS (or taken from
+    `svc`); the stream is the first `nreq` requests of the seeded sequence,
+    or as many as fit `work_s` seconds of sequential work; the arrival rate
+    is `load` times the capacity those times imply for serving the drawn
+    requests one after another.  Latency is submit -> completion, measured
+    by the server.  `mode`: 'batching' (continuous batching, `slots` RHS
+    slots per request shape) or 'contexts' (one batched solve per request).
+    A progress line goes to stderr at least every 30 s."""
     import threading
     import torch
     import workloads as W
     from paper_2104_05615_amd import Server
     rng = np.random.default_rng(seed)
+    cap = nreq if nreq is not None else 100000
     reqs = []
-    for i in range(nreq):
+    for i in range(cap if nreq is not None else 1000):
         reqs.append((volumes[int(rng.integers(len(volumes)))], float(masses[int(rng.integers(len(masses)))]),
                      int(rng.integers(1, max_rhs + 1))))
-    gaps = rng.exponential(1.0, size=nreq)
+    gaps = rng.exponential(1.0, size=len(reqs))
     srv = Server(0, int(budget_gb) << 30, max_inflight)
+    srv.set_mode(mode, slots)
     fid = {}
     for k, name in enumerate(volumes):
         dims, Ls, sub = SERVE_VOLUMES[name]
@@ -151,25 +157,39 @@ def serve_stream(volumes, masses, max_rhs, nreq, seed=105, load=0.75, budget_gb=
         stream.synchronize()
         return srv.submit(fid[name], Ls, 1.5, 0.5, 1.8, mf, sub, nrhs, b.data_ptr(), x.data_ptr(), **solver)
 
-    # service time per (volume, mass), one RHS, alone (also creates the contexts)
-    svc = {}
-    for name, mf in sorted({(r[0], r[1]) for r in reqs}):
-        b, x = make(name, 1, 1)
-        st, stats, lat = srv.wait(submit(name, mf, 1, b, x))
-        assert st == 0, (name, mf, st)
-        svc[(name, mf)] = lat / 1e3
-        log(f"[serve] alone {name} mf={mf}: {lat / 1e3:.3f}s, {stats[0].outer_iters} iters")
+    # service time per (volume, mass), one RHS, alone (also creates the
+    # contexts), measured for the (volume, mass) pairs the stream reaches
+    svc = dict(svc or {})
+    total, n = 0.0, 0
+    for name, mf, k in reqs:
+        if (name, mf) not in svc:
+            b, x = make(name, 1, 1)
+            log(f"[serve] measuring {name} mf={mf} alone")
+            st, stats, lat = srv.wait(submit(name, mf, 1, b, x))
+            assert st == 0, (name, mf, st)
+            svc[(name, mf)] = lat / 1e3
+            log(f"[serve] alone {name} mf={mf}: {lat / 1e3:.3f}s, {stats[0].outer_iters} iters")
+        if nreq is None and n > 0 and total + svc[(name, mf)] * k > work_s:
+            break
+        total += svc[(name, mf)] * k
+        n += 1
+    reqs = reqs[:n]
+    gaps = gaps[:n]
+    nreq = len(reqs)
     work = sum(svc[(n, m)] * k for n, m, k in reqs)
     capacity = nreq / work
     lam = load * capacity
-    log(f"[serve] {nreq} requests, sequential work {work:.1f}s, capacity {capacity:.3f}/s, "
+    log(f"[serve] {mode}: {nreq} requests, sequential work {work:.1f}s, capacity {capacity:.3f}/s, "
         f"arrival rate {lam:.3f}/s")
     results = [None] * nreq
     pending = []
     cv = threading.Condition()
     done_submitting = [False]
+    ndone = [0]
+    t0 = time.perf_counter()
 
     def waiter():
+        last = time.perf_counter()
         while True:
             with cv:
                 while not pending and not done_submitting[0]:
@@ -177,8 +197,19 @@ def serve_stream(volumes, masses, max_rhs, nreq, seed=105, load=0.75, budget_gb=
                 if not pending:
                     return
                 i, t, bufs = pending.pop(0)
+            while not srv.poll(t):
+                time.sleep(0.05)
+                if time.perf_counter() - last > 30:
+                    last = time.perf_counter()
+                    inf = srv.info()
+                    r = reqs[i]
+                    log(f"[serve] {time.perf_counter() - t0:.0f}s: {ndone[0]} of {nreq} done, waiting on request "
+                        f"{i} ({r[0]}, mf={r[1]}, {r[2]} RHS), {inf['inflight']} in flight, "
+                        f"{inf['waiting']} queued")
             results[i] = srv.wait(t)
             del bufs
+            ndone[0] += 1
+            last = time.perf_counter()
             r = reqs[i]
             log(f"[serve] request {i} ({r[0]}, mf={r[1]}, {r[2]} RHS) done: status {results[i][0]}, "
                 f"latency {results[i][2] / 1e3:.2f}s")
@@ -207,17 +238,20 @@ def serve_stream(volumes, masses, max_rhs, nreq, seed=105, load=0.75, budget_gb=
     lats = np.array([r[2] for r in results]) / 1e3
     ok = all(r[0] == 0 for r in results)
     nrhs_tot = sum(r[2] for r in reqs)
-    out = {"requests": nreq, "rhs": nrhs_tot, "all_converged": ok,
+    out = {"design": mode, "slots": slots if mode == "batching" else None,
+           "requests": nreq, "rhs": nrhs_tot, "all_converged": ok,
            "p50_s": float(np.percentile(lats, 50)), "p99_s": float(np.percentile(lats, 99)),
            "mean_s": float(lats.mean()), "max_s": float(lats.max()),
            "solves_per_s": nreq / makespan, "rhs_per_s": nrhs_tot / makespan, "makespan_s": makespan,
            "arrival_rate_per_s": lam, "capacity_sequential_per_s": capacity, "load": load,
+           "sequential_work_s": work,
            "max_inflight": max_inflight, "budget_bytes": info["budget"], "peak_bytes": info["bytes_peak"],
            "peak_inflight": info["peak_inflight"], "contexts": info["contexts"], "evictions": info["evictions"],
            "mix": {"volumes": volumes, "masses": masses, "rhs": [1, max_rhs], "seed": seed,
                    "service_alone_s": {f"{n} mf={m}": v for (n, m), v in svc.items()}}}
-    log(f"[serve] p50 {out['p50_s']:.3f}s p99 {out['p99_s']:.3f}s, {out['solves_per_s']:.3f} solves/s, "
+    log(f"[serve] {mode}: p50 {out['p50_s']:.3f}s p99 {out['p99_s']:.3f}s, {out['solves_per_s']:.3f} solves/s, "
         f"peak in flight {info['peak_inflight']}")
+    out["_svc"] = svc
     return out
 
 
@@ -457,7 +491,11 @@ def main():
                          "when they would not fit")
     ap.add_argument("--oracle-check", action="store_true",
                     help="relative residual of the MSPCG solution by the FP64 oracle on the host")
-    ap.add_argument("--requests", type=int, default=None, help="serving stream length")
+    ap.add_argument("--requests", type=int, default=None, help="serving stream length (default: --serve-work)")
+    ap.add_argument("--serve-work", type=float, default=300.0,
+                    help="serving stream: as many requests as fit this many seconds of sequential work")
+    ap.add_argument("--serve-design", default="batching", choices=["batching", "contexts", "both"])
+    ap.add_argument("--slots", type=int, default=8, help="RHS slots per shape (continuous batching)")
     ap.add_argument("--budget-gb", type=int, default=200, help="HBM budget of the request server (GB)")
     ap.add_argument("--serve-sample", type=int, default=10,
                     help="requests of the serving sample in solve mode (0: none)")
@@ -473,9 +511,16 @@ def main():
         return kernels_bench(args)
     if args.mode == "serve":
         import torch  # noqa: F401
-        r = serve_stream(nreq=args.requests or 200, budget_gb=args.budget_gb, **SERVE_FULL)
-        print(json.dumps({"metric": "serving p50/p99 latency and solves/s", "unit": "s", "value": r["p99_s"],
-                          "serve": r}), flush=True)
+        designs = ["batching", "contexts"] if args.serve_design == "both" else [args.serve_design]
+        out, svc = {}, None
+        for d in designs:
+            r = serve_stream(nreq=args.requests, work_s=args.serve_work, budget_gb=args.budget_gb, mode=d,
+                             slots=args.slots, svc=svc, **SERVE_FULL)
+            svc = r.pop("_svc")
+            out[d] = r
+            print(json.dumps({"design": d, "serve": r}), file=sys.stderr, flush=True)
+        print(json.dumps({"metric": "serving p50/p99 latency and solves/s", "unit": "s",
+                          "value": out[designs[0]]["p99_s"], "serve": out}), flush=True)
         return
 
     import torch
@@ -672,8 +717,10 @@ def main():
     if args.serve_sample > 0 and fits("serving_sample", 45.0):
         del s
         r = serve_stream(nreq=args.serve_sample, **SERVE_SAMPLE)
+        r.pop("_svc")
         line["p50_p99"] = {"p50_s": r["p50_s"], "p99_s": r["p99_s"], "solves_per_s": r["solves_per_s"],
-                           "sample": "serving sample: Poisson stream of %d requests over 8^4x8 and 16^3x32x12, "
+                           "sample": "serving sample, continuous batching: Poisson stream of %d requests over "
+                                     "8^4x8 and 16^3x32x12, "
                                      "mf in {0.1, 0.01}, 1-3 RHS each, load %.2f of the measured sequential capacity"
                                      % (r["requests"], r["load"]),
                            "detail": r}

@@ -48,6 +48,7 @@ typedef struct mspcg_ctx* mspcg_t;
 typedef enum {
   MSPCG_OK = 0,
   MSPCG_NOT_CONVERGED = 1,     /* result and stats are filled in */
+  MSPCG_BUSY = 2,              /* mspcg_cb_submit: every slot is taken (nothing was queued) */
   MSPCG_ERR_INVALID_ARG = -1,
   MSPCG_ERR_BAD_TILING = -2,
   MSPCG_ERR_NO_GAUGE = -3,
@@ -274,6 +275,59 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
 mspcg_status mspcg_apply_device_noalloc(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
                                         void* hip_stream);
 
+/* Residual history of the last single-RHS solve on this handle
+ * (mspcg_solve / mspcg_solve_device, Alg. 1): out[k] = |r_k| / |b| for
+ * k = 0 .. min(max, count) - 1, r_k the iterated residual after k outer
+ * iterations (r_0 = b - A x0; before a reliable update replaces it), the
+ * quantity the paper plots against the outer iteration (Fig. residual-rbc,
+ * Fig. residual-cal).  pap (nullable, max entries): pap[k] = <p_k, A p_k> /
+ * |b|^2 of outer iteration k + 1 (0 past the last one); with out they give
+ * the CG coefficients alpha_k = |r_k|^2 / <p_k, A p_k> and beta_k =
+ * |r_k+1|^2 / |r_k|^2 of a plain CG solve, whose Lanczos matrix estimates
+ * the extreme eigenvalues of A.  *count = the number of residuals the solve
+ * recorded (outer iterations + 1; 0 for a zero source).  Errors:
+ * INVALID_ARG (NULL handle or count, NULL out with max > 0, max < 0). */
+mspcg_status mspcg_get_history(mspcg_t h, double* out, double* pap, int32_t max, int32_t* count);
+
+/* Continuous batching (serving extension; the paper's solver is unchanged).
+ * A session is a batched solve over `slots` right-hand-side slots of this
+ * handle that right-hand sides enter and leave while others iterate: every
+ * kernel of an outer iteration runs once for all slots (one launch per
+ * operator, masked per slot on the device, the iteration pair captured once
+ * in a HIP graph and replayed), and a submitted source starts at the next
+ * step with the start-up sequence of Alg. 1 run for the joining slots only.
+ * Each slot's arithmetic is independent of the other slots, so its solution
+ * and statistics are the same as those of mspcg_solve_batch_device for that
+ * source alone.  The solver parameters are those set when the session
+ * opens.  While a session is open every other call that uses or changes this
+ * handle's state (set_*, solve*, apply*, autotune, ...) returns INVALID_ARG,
+ * and mspcg_set_mfma fails for the process.  A handle is not thread-safe:
+ * one thread drives its session.
+ *
+ * mspcg_cb_open   sizes the workspace for `slots` RHS (device memory as
+ *                 mspcg_footprint(h, slots)); stream NULL = the handle's.
+ * mspcg_cb_submit queues one source: b and x are device FP64 fields of the
+ *                 canonical layout; b must stay valid until the slot has
+ *                 started (the next step) and x until mspcg_cb_poll reports
+ *                 the slot done.  Returns the slot, or MSPCG_BUSY when every
+ *                 slot is taken.
+ * mspcg_cb_step   starts the pending slots, runs one pair of outer
+ *                 iterations for all running slots, and writes x of every
+ *                 slot that has finished (converged, breakdown, or the
+ *                 iteration limit); returns when that is done, with the
+ *                 number of slots still running and still pending.
+ * mspcg_cb_poll   done = 1 and the slot's statistics (ms_total: from its
+ *                 start to the step that finished it) once it has finished;
+ *                 the slot is free again after that call.
+ * mspcg_cb_close  ends the session (running slots are abandoned).
+ * Errors: INVALID_ARG (no session / one already open / slot out of range /
+ * NULL), the errors of mspcg_solve_batch_device. */
+mspcg_status mspcg_cb_open(mspcg_t h, int32_t slots, void* hip_stream);
+mspcg_status mspcg_cb_submit(mspcg_t h, const double* b, double* x, int32_t* slot);
+mspcg_status mspcg_cb_step(mspcg_t h, int32_t* running, int32_t* pending);
+mspcg_status mspcg_cb_poll(mspcg_t h, int32_t slot, int32_t* done, mspcg_stats* st);
+mspcg_status mspcg_cb_close(mspcg_t h);
+
 /* Kernel timing.  With profiling on, the library brackets every launch of its
  * hop kernels with HIP events on the stream they run on; mspcg_get_kernel_time
  * returns the number of timed launches and their summed duration in ms for a
@@ -367,15 +421,14 @@ mspcg_status mspcg_footprint(mspcg_t h, int32_t nrhs, int64_t* estimate, int64_t
  *
  * Requests (a batched solve: field, Mobius parameters, tiling, solver
  * parameters, nrhs device sources and solutions) are admitted in arrival
- * order while fewer than max_inflight run and their device footprint fits
- * the HBM budget; each admitted request runs on its own worker thread and
- * HIP stream, so requests overlap on the device, and a request that arrives
- * while others run is admitted as soon as a slot and the memory free up
- * (continuous batching).  Solver contexts stay resident between requests,
- * one per (field, Ls, b, c, M5, mf, tiling) in use, and are reused by later
- * requests of the same shape; idle contexts are evicted least recently used
- * when the budget needs their memory.  A request's result does not depend
- * on what runs beside it.
+ * order while their device footprint fits the HBM budget.  By default they
+ * are continuously batched (mspcg_server_set_mode): the right-hand sides of
+ * requests of one shape share the slots of one running batched solve and
+ * enter it as earlier ones finish, and solves of different shapes run
+ * concurrently on their own threads and streams.  Solver state stays
+ * resident between requests and is evicted least recently used when the
+ * budget needs its memory.  A request's result does not depend on what runs
+ * beside it.
  * ------------------------------------------------------------------------- */
 typedef struct mspcg_server* mspcg_server_t;
 
@@ -427,6 +480,21 @@ mspcg_status mspcg_server_wait(mspcg_server_t s, int64_t ticket, mspcg_stats* st
  * mspcg_set_graphs; off by default, since the caller's threads may
  * synchronize the device at any time).  Errors: INVALID_ARG (NULL). */
 mspcg_status mspcg_server_set_graphs(mspcg_server_t s, int32_t on);
+
+/* How the server runs admitted requests (only while none is in flight):
+ * mode 1 (default) continuous batching -- one engine per request shape
+ * (field, Mobius parameters, tiling and solver parameters), an open
+ * mspcg_cb_* session of `slots` right-hand-side slots driven by a thread and
+ * stream of its own; a request's right-hand sides queue at its shape's
+ * engine and enter slots as earlier ones finish, while the others keep
+ * iterating; at most max_inflight engines are busy at once, and an engine
+ * holds mspcg_footprint(slots) bytes of the budget; mode 0 -- one resident
+ * context per shape and a worker thread and stream per admitted request,
+ * which runs the request as one batched solve (at most max_inflight at
+ * once).  In both modes a right-hand side's solution does not depend on what
+ * runs beside it.  Errors: INVALID_ARG (mode, slots outside [1, 1024],
+ * requests in flight). */
+mspcg_status mspcg_server_set_mode(mspcg_server_t s, int32_t mode, int32_t slots);
 
 /* Counters of the server. */
 mspcg_status mspcg_server_info(mspcg_server_t s, mspcg_server_stats* info);

@@ -35,6 +35,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- constants
 MSPCG_OK = 0
 MSPCG_NOT_CONVERGED = 1
+MSPCG_BUSY = 2
 MSPCG_ERR_INVALID_ARG = -1
 MSPCG_ERR_BAD_TILING = -2
 MSPCG_ERR_NO_GAUGE = -3
@@ -107,6 +108,7 @@ _SIGS = {
     "mspcg_set_log": [_h, _i32],
     "mspcg_set_mfma": [_i32],
     "mspcg_server_set_graphs": [_h, _i32],
+    "mspcg_server_set_mode": [_h, _i32, _i32],
     "mspcg_footprint": [_h, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "mspcg_server_create": [ctypes.POINTER(_h), _i32, ctypes.c_int64, _i32],
     "mspcg_server_destroy": [_h],
@@ -121,6 +123,12 @@ _SIGS = {
     "mspcg_apply": [_h, _i32, ctypes.c_int, _p, _p],
     "mspcg_apply_device": [_h, _i32, ctypes.c_int, _p, _p, _p],
     "mspcg_apply_device_noalloc": [_h, _i32, ctypes.c_int, _p, _p, _p],
+    "mspcg_get_history": [_h, _p, _p, _i32, ctypes.POINTER(_i32)],
+    "mspcg_cb_open": [_h, _i32, _p],
+    "mspcg_cb_submit": [_h, _p, _p, ctypes.POINTER(_i32)],
+    "mspcg_cb_step": [_h, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "mspcg_cb_poll": [_h, _i32, ctypes.POINTER(_i32), ctypes.POINTER(mspcg_stats)],
+    "mspcg_cb_close": [_h],
     "mspcg_set_profiling": [_h, _i32],
     "mspcg_get_kernel_time": [_h, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_d)],
 }
@@ -359,6 +367,45 @@ class MSPCG:
         _check(mspcg_apply_device_noalloc(self._h, OPS[op] if isinstance(op, str) else int(op),
                                           PREC[prec] if isinstance(prec, str) else int(prec), in_ptr, out_ptr, stream))
 
+    def history(self, pap=False):
+        """|r_k| / |b| of the last single-RHS solve, k = 0 .. outer iterations;
+        with pap also <p_k, A p_k> / |b|^2 of every outer iteration."""
+        n = _i32()
+        _check(mspcg_get_history(self._h, None, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        pp = np.zeros(max(n.value, 1))
+        _check(mspcg_get_history(self._h, out.ctypes.data, pp.ctypes.data, n.value, ctypes.byref(n)))
+        return (out[:n.value], pp[:max(n.value - 1, 0)]) if pap else out[:n.value]
+
+    # continuous batching (mspcg_cb_*): slots that sources enter and leave
+    def cb_open(self, slots, stream=None):
+        _check(mspcg_cb_open(self._h, int(slots), stream))
+
+    def cb_submit(self, b_ptr, x_ptr):
+        """The slot the source took, or None when every slot is taken."""
+        s = _i32()
+        st = mspcg_cb_submit(self._h, b_ptr, x_ptr, ctypes.byref(s))
+        if st == MSPCG_BUSY:
+            return None
+        _check(st)
+        return s.value
+
+    def cb_step(self):
+        """(running, pending) after one step."""
+        r, p = _i32(), _i32()
+        _check(mspcg_cb_step(self._h, ctypes.byref(r), ctypes.byref(p)))
+        return r.value, p.value
+
+    def cb_poll(self, slot):
+        """Stats of the slot once it has finished (the slot is then free), else None."""
+        d = _i32()
+        a = mspcg_stats()
+        _check(mspcg_cb_poll(self._h, int(slot), ctypes.byref(d), ctypes.byref(a)))
+        return _stats(a.status, a) if d.value else None
+
+    def cb_close(self):
+        _check(mspcg_cb_close(self._h))
+
     def set_profiling(self, on=True, stride=1):
         """HIP-event timing of the hop stages; stride N > 1 times one launch in N of each stage."""
         _check(mspcg_set_profiling(self._h, (max(1, int(stride)) if on else 0)))
@@ -425,6 +472,10 @@ class Server:
 
     def set_graphs(self, on=True):
         _check(mspcg_server_set_graphs(self._h, 1 if on else 0))
+
+    def set_mode(self, mode="batching", slots=8):
+        """'batching' (continuous batching, default) or 'contexts' (one batched solve per request)."""
+        _check(mspcg_server_set_mode(self._h, 1 if mode == "batching" else 0, int(slots)))
 
     def info(self):
         i = mspcg_server_stats()

@@ -108,6 +108,8 @@ void pack_field(hipStream_t st, const FieldPtr& out, const double* canon, int64_
                 const Batch& bt = Batch());
 void unpack_field(hipStream_t st, double* canon, const FieldPtr& in, int64_t nsites, int Ls,
                   const Batch& bt = Batch());
+// p[0..n) = v (a kernel, so that graph capture records no memset)
+void fill_int(hipStream_t st, int* p, int n, int v);
 // zero bytes_per_rhs bytes of every masked RHS (bytes_per_rhs % 16 == 0)
 void zero_batched(hipStream_t st, void* data, int64_t bytes_per_rhs, const Batch& bt);
 // gauge: canonical [T][Z][Y][X][4][3][3] complex FP64 -> [parity][mu][vh][10] double2 / float2 / half2
@@ -157,10 +159,13 @@ struct CtlParams {
   double tol, delta;
   int maxiter;
 };
-// from scal[TMP] = |b|^2: status, active, bnorm; scal[TMP] = 0
-void ctl_init(hipStream_t st, const Ctl& c, double* scal, int n);
-// starting residual: scal[R64] (has_x0) or |b|^2; rmax, rr
-void ctl_start(hipStream_t st, const Ctl& c, const double* scal, int n, bool has_x0);
+// from scal[TMP] = |b|^2: status, active, bnorm; scal[TMP] = 0.  With a
+// join mask only the RHS r with join[r] != 0 start (the others keep their
+// state), and join[r] becomes active[r]: the start-up kernels after it use
+// join as their mask.
+void ctl_init(hipStream_t st, const Ctl& c, double* scal, int n, int* join);
+// starting residual: scal[R64] (has_x0) or |b|^2; rmax, rr (RHS of join only)
+void ctl_start(hipStream_t st, const Ctl& c, const double* scal, int n, bool has_x0, const int* join);
 // after the iterated |r|^2 (scal[RR]) and pAp (scal[PAP]): breakdown,
 // iteration count, reliable-update decision
 void ctl_iterate(hipStream_t st, const Ctl& c, const double* scal, int n, const CtlParams& p);

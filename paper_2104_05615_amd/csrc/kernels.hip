@@ -88,6 +88,8 @@ static void launch_hop_mf(hipStream_t st, const Geo& geo, int64_t nblocks, const
                           const FieldPtr* w, int Ls, int ns, bool dagger, const Epilogue& epi, const Batch& bt,
                           const Sched& sc) {
   using T = calc_t<S>;
+  if (epi.dot_partial && !(dagger && w))
+    throw std::runtime_error("hop: the fused dot belongs to an adjoint hop with a centre field");
   const bool tileB = w != nullptr && !epi.w_identity && epi.E0 != nullptr;
   const size_t lds = site_lds_bytes<T>(ns, Ls, tileB, MF, UsesMfma<S>::half_ops);
   Field<S> wf = w ? typed<S>(*w) : Field<S>{};
@@ -429,6 +431,17 @@ __global__ void k_zero(uint4* data, int64_t n16, const int* mask) {
     d[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void fill_int(hipStream_t st, int* p, int n, int v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  LAUNCH_CHECK();
+}
+
 void zero_batched(hipStream_t st, void* data, int64_t bytes_per_rhs, const Batch& bt) {
   if (bytes_per_rhs % 16) throw std::runtime_error("zero_batched: size must be a multiple of 16 bytes");
   const int64_t n16 = bytes_per_rhs / 16;
@@ -733,9 +746,9 @@ void finish(hipStream_t st, const double* p1, const double* p2, int64_t n, doubl
 // one, on convergence, or at the iteration limit; convergence is decided on
 // the true residual that the update recomputes.
 
-__global__ void k_ctl_init(Ctl c, double* scal, int n) {
+__global__ void k_ctl_init(Ctl c, double* scal, int n, int* join) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  if (r >= n || (join && !join[r])) return;
   double* sc = scal + (int64_t)r * SLOT_COUNT;
   const double bn2 = sc[SLOT_TMP];
   c.iters[r] = 0;
@@ -759,11 +772,12 @@ __global__ void k_ctl_init(Ctl c, double* scal, int n) {
     c.bnorm[r] = sqrt(bn2);
   }
   sc[SLOT_TMP] = 0.0;   // beta of the first search direction p = z + 0 p
+  if (join) join[r] = c.active[r];   // the start-up kernels that follow run on these RHS only
 }
 
-__global__ void k_ctl_start(Ctl c, const double* scal, int n, int has_x0) {
+__global__ void k_ctl_start(Ctl c, const double* scal, int n, int has_x0, const int* join) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n || !c.active[r]) return;
+  if (r >= n || !c.active[r] || (join && !join[r])) return;
   const double bn = c.bnorm[r];
   const double rr = has_x0 ? scal[(int64_t)r * SLOT_COUNT + SLOT_R64] : bn * bn;
   c.rr[r] = has_x0 ? rr : bn * bn;
@@ -830,13 +844,13 @@ __global__ void __launch_bounds__(1024) k_ctl_after_update(Ctl c, double* scal, 
 
 static unsigned ctl_blocks(int n) { return (unsigned)((n + 255) / 256); }
 
-void ctl_init(hipStream_t st, const Ctl& c, double* scal, int n) {
-  hipLaunchKernelGGL(k_ctl_init, dim3(ctl_blocks(n)), dim3(256), 0, st, c, scal, n);
+void ctl_init(hipStream_t st, const Ctl& c, double* scal, int n, int* join) {
+  hipLaunchKernelGGL(k_ctl_init, dim3(ctl_blocks(n)), dim3(256), 0, st, c, scal, n, join);
   LAUNCH_CHECK();
 }
 
-void ctl_start(hipStream_t st, const Ctl& c, const double* scal, int n, bool has_x0) {
-  hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(n)), dim3(256), 0, st, c, scal, n, has_x0 ? 1 : 0);
+void ctl_start(hipStream_t st, const Ctl& c, const double* scal, int n, bool has_x0, const int* join) {
+  hipLaunchKernelGGL(k_ctl_start, dim3(ctl_blocks(n)), dim3(256), 0, st, c, scal, n, has_x0 ? 1 : 0, join);
   LAUNCH_CHECK();
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -355,6 +357,7 @@ struct EventPair {
   hipEvent_t a, b;
 };
 
+struct CBSession;   // an open continuous-batching session (defined with the batched solver)
 }  // namespace
 
 void mspcg::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
@@ -400,6 +403,11 @@ struct mspcg_ctx {
     size_t cap = 0, off = 0;
   } arena;
   std::map<std::string, std::unique_ptr<DevBuf>> arena_ws;
+  // open continuous-batching session (mspcg_cb_*), or null
+  std::shared_ptr<CBSession> cb;
+  // |r_k| / |b| of the last single-RHS solve, k = 0, 1, ... (iterated
+  // residuals), and <p_k, A p_k> / |b|^2 of its outer iterations
+  std::vector<double> history, history_pap;
   double* h_scal = nullptr;   // pinned
   int* h_flag = nullptr;      // pinned: RHS still active, one slot per graph replay in flight
   // pinned bounce buffer: every transfer between host memory the caller owns
@@ -442,6 +450,7 @@ struct mspcg_ctx {
     if (hip_ready) {
       (void)hipSetDevice(device);
       (void)hipStreamSynchronize(stream);
+      cb.reset();
       ws.clear();
       std::unique_lock<std::shared_mutex> lk(g_capture_gate);
       for (auto& e : ev_pool) {
@@ -1151,6 +1160,8 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
   mspcg_stats S;
   std::memset(&S, 0, sizeof(S));
   mspcg_status status = MSPCG_NOT_CONVERGED;
+  h->history.clear();
+  h->history_pap.clear();
   if (bnorm2 == 0.0) {
     HIPCHK(hipMemsetAsync(x64.data, 0, (size_t)n5 * 192, st));
     status = MSPCG_OK;
@@ -1165,6 +1176,7 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
     double rmax = std::sqrt(rr);
     const double delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.0;
     const double* rr_partial = nullptr;
+    h->history.push_back(std::sqrt(rr) / bnorm);
 
     // z = M r ; rho = <r, z>
     auto apply_precond = [&](bool with_rold) {
@@ -1212,6 +1224,8 @@ mspcg_status solve_impl(mspcg_ctx* h, const double* b_dev, double* x_dev, const 
       }
       const double rn = std::sqrt(rr);
       S.iter_rel_resid = rn / bnorm;
+      h->history.push_back(rn / bnorm);
+      h->history_pap.push_back(pap / bnorm2);
       rmax = std::max(rmax, rn);
       if (h->log_every > 0 && it % h->log_every == 0)
         std::fprintf(stderr, "[mspcg] iteration %d  |r|/|b| = %.3e  reliable updates %d\n", it, rn / bnorm,
@@ -1351,107 +1365,142 @@ struct GraphGuard {
   }
 };
 
-mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, double* x_dev, const double* x0_dev,
-                              hipStream_t st, mspcg_stats* stats) {
-  const mspcg_solver_params& sp = h->sp;
-  const Prec O = to_prec(sp.outer_prec);
-  const Prec I = to_prec(sp.inner_prec);
-  const bool pre = sp.use_precond != 0;
-  const bool pr = sp.beta_rule == 0;
-  const int64_t vh = h->lat.vh, n5 = h->n5(), nreal = n5 * 24;
-  const int Ls = h->Ls;
-  const int n = nrhs;
-  if (pre && !h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "MSPCG needs mspcg_set_subdomains");
-  if (pre && sp.inner_iters < 1) throw Error(MSPCG_ERR_INVALID_ARG, "MSPCG needs inner_iters >= 1");
-  const bool use_graph = h->graphs && !h->profiling;
-
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, st));
-
-  double* scal = h->scal(n);
-  const int64_t nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4));
-  const int64_t nbl64 = blas_blocks(nreal / 2);
-  double* p_upd = h->partial("upd", nbl * n);
-  double* p_ru = h->partial("ru", nbl64 * n);
-  double* p_b = h->partial("b", nbl64 * n);
-  const int64_t bps_hop = full_blocks(vh, Ls, O);
-  double* p_pap = h->partial("pap", bps_hop * n);
-  int64_t nz = nbl;
-  if (pre) nz = h->precond_partials(O, I);
-  double* p_z1 = h->partial("z1", nz * n);
-  double* p_z2 = h->partial("z2", nz * n);
-
-  // per-RHS control state
-  int* ci = h->buf("ctl.i", (size_t)(8 * n + 1) * sizeof(int)).as<int>();
-  double* cd = h->buf("ctl.d", (size_t)3 * n * sizeof(double)).as<double>();
+// ---------------------------------------------------------------- batched solver engine
+// The batched solver over n RHS slots: every kernel of an iteration runs once
+// for all slots, masked by the per-slot control state on the device
+// (k_ctl_*).  Slots start between iteration pairs through the start-up
+// sequence masked to them (join), so right-hand sides can enter while others
+// iterate (continuous batching); the one-shot batched solve starts every slot
+// at once and runs pairs until none is active.  Each slot's arithmetic never
+// depends on the other slots, so a slot's solution is the same whichever
+// slots run beside it and whenever it starts.
+struct BatchEngine {
+  mspcg_ctx* h;
+  const int n;
+  const hipStream_t st;
+  const std::string tag;   // workspace names ("s" for the one-shot solve, "cb" for an open session)
+  mspcg_solver_params sp;
+  Prec O, I;
+  bool pre, pr, use_graph;
+  int64_t vh, n5, nreal, nbl, nbl64, bps_hop, nz, bytes64, bytesO;
+  int Ls;
+  double *scal, *p_upd, *p_ru, *p_b, *p_pap, *p_z1, *p_z2;
+  int* ci = nullptr;
+  double* cd = nullptr;
+  int* join = nullptr;
   Ctl c;
-  c.active = ci;
-  c.ru = ci + n;
-  c.bzero = ci + 2 * n;
-  c.status = ci + 3 * n;
-  c.iters = ci + 4 * n;
-  c.rus = ci + 5 * n;
-  c.precs = ci + 6 * n;
-  c.nactive = ci + 8 * n;
-  c.bnorm = cd;
-  c.rmax = cd + n;
-  c.rr = cd + 2 * n;
   CtlParams cp;
-  cp.tol = sp.tol;
-  cp.delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.0;
-  cp.maxiter = sp.maxiter;
-  Batch all, act, rum, bz;
-  all.n = act.n = rum.n = bz.n = n;
-  act.mask = c.active;
-  rum.mask = c.ru;
-  bz.mask = c.bzero;
-
-  FieldPtr b64 = h->field("s.b64", Prec::F64, vh, n), x64 = h->field("s.x64", Prec::F64, vh, n);
-  FieldPtr q64 = h->field("s.q64", Prec::F64, vh, n);
-  FieldPtr x = O == Prec::F64 ? x64 : h->field("s.x", O, vh, n);
-  FieldPtr rA = h->field("s.rA", O, vh, n), rB = h->field("s.rB", O, vh, n);
-  FieldPtr z = pre ? h->field("s.z", O, vh, n) : rA;
-  FieldPtr p = h->field("s.p", O, vh, n), q = h->field("s.q", O, vh, n), t0 = h->field("s.t0", O, vh, n);
-  const int64_t bytes64 = n5 * 192, bytesO = n5 * (int64_t)chunk_bytes(O);
-
-  pack_field(st, b64, b_dev, vh, Ls, all);
-  if (x0_dev) pack_field(st, x64, x0_dev, vh, Ls, all);
-  else zero_batched(st, x64.data, bytes64, all);
-  if (O == Prec::F32) zero_batched(st, x.data, bytesO, all);
-  zero_batched(st, p.data, bytesO, all);
-
-  dot2(st, Prec::F64, b64.data, b64.data, nullptr, nreal, p_b, nullptr, nbl64, all);
-  finish(st, p_b, nullptr, nbl64, scal, FIN_STORE, SLOT_TMP, all);
-  ctl_init(st, c, scal, n);
-  zero_batched(st, x64.data, bytes64, bz);
-
+  Batch all, act, rum, bz, jn;
+  FieldPtr b64, x64, q64, x, rA, rB, z, p, q, t0;
   FieldPtr* r = &rA;
   FieldPtr* rold = &rB;
+  GraphGuard gg;
+  bool graph_tried = false, graph = false;
+
+  BatchEngine(mspcg_ctx* hh, int nn, hipStream_t s, const std::string& t) : h(hh), n(nn), st(s), tag(t) {
+    sp = h->sp;
+    O = to_prec(sp.outer_prec);
+    I = to_prec(sp.inner_prec);
+    pre = sp.use_precond != 0;
+    pr = sp.beta_rule == 0;
+    vh = h->lat.vh;
+    n5 = h->n5();
+    nreal = n5 * 24;
+    Ls = h->Ls;
+    if (pre && !h->have_tiling) throw Error(MSPCG_ERR_BAD_TILING, "MSPCG needs mspcg_set_subdomains");
+    if (pre && sp.inner_iters < 1) throw Error(MSPCG_ERR_INVALID_ARG, "MSPCG needs inner_iters >= 1");
+    use_graph = h->graphs && !h->profiling;
+    scal = h->scal(n);
+    nbl = blas_blocks(nreal / (O == Prec::F64 ? 2 : 4));
+    nbl64 = blas_blocks(nreal / 2);
+    p_upd = h->partial("upd", nbl * n);
+    p_ru = h->partial("ru", nbl64 * n);
+    p_b = h->partial("b", nbl64 * n);
+    bps_hop = full_blocks(vh, Ls, O);
+    p_pap = h->partial("pap", bps_hop * n);
+    nz = pre ? h->precond_partials(O, I) : nbl;
+    p_z1 = h->partial("z1", nz * n);
+    p_z2 = h->partial("z2", nz * n);
+    ci = h->buf(tag + ".ctl.i", (size_t)round16((int64_t)(8 * n + 1) * sizeof(int))).as<int>();
+    cd = h->buf(tag + ".ctl.d", (size_t)3 * n * sizeof(double)).as<double>();
+    join = h->buf(tag + ".ctl.join", (size_t)n * sizeof(int)).as<int>();
+    c.active = ci;
+    c.ru = ci + n;
+    c.bzero = ci + 2 * n;
+    c.status = ci + 3 * n;
+    c.iters = ci + 4 * n;
+    c.rus = ci + 5 * n;
+    c.precs = ci + 6 * n;
+    c.nactive = ci + 8 * n;
+    c.bnorm = cd;
+    c.rmax = cd + n;
+    c.rr = cd + 2 * n;
+    cp.tol = sp.tol;
+    cp.delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.0;
+    cp.maxiter = sp.maxiter;
+    all.n = act.n = rum.n = bz.n = jn.n = n;
+    act.mask = c.active;
+    rum.mask = c.ru;
+    bz.mask = c.bzero;
+    jn.mask = join;
+    b64 = h->field(tag + ".b64", Prec::F64, vh, n);
+    x64 = h->field(tag + ".x64", Prec::F64, vh, n);
+    q64 = h->field(tag + ".q64", Prec::F64, vh, n);
+    x = O == Prec::F64 ? x64 : h->field(tag + ".x", O, vh, n);
+    rA = h->field(tag + ".rA", O, vh, n);
+    rB = h->field(tag + ".rB", O, vh, n);
+    z = pre ? h->field(tag + ".z", O, vh, n) : rA;
+    p = h->field(tag + ".p", O, vh, n);
+    q = h->field(tag + ".q", O, vh, n);
+    t0 = h->field(tag + ".t0", O, vh, n);
+    bytes64 = n5 * 192;
+    bytesO = n5 * (int64_t)chunk_bytes(O);
+    // every slot idle: no kernel of an iteration touches it
+    zero_batched(st, ci, round16((int64_t)(8 * n + 1) * sizeof(int)), Batch());
+  }
+
+  // slot i of a batched field
+  FieldPtr slot(const FieldPtr& f, int i) const {
+    FieldPtr v = f;
+    v.data = (char*)f.data + (size_t)i * (size_t)f.stride * chunk_bytes(f.prec);
+    if (f.scale) v.scale = f.scale + (size_t)i * (size_t)f.stride;
+    return v;
+  }
+
   // r = b - A x (FP64) for the masked RHS; lower-precision copy into *r
-  auto true_residual = [&](const Batch& m) {
+  void true_residual(const Batch& m) {
     h->A_op(st, Prec::F64, q64, x64, "A64", nullptr, m);
     residual64(st, (const double*)b64.data, (const double*)q64.data, O == Prec::F64 ? (double*)r->data : nullptr,
                O == Prec::F32 ? (float*)r->data : nullptr, n5, p_ru, nbl64, m);
     finish(st, p_ru, nullptr, nbl64, scal, FIN_STORE, SLOT_R64, m);
-  };
-  if (x0_dev) true_residual(act);
-  else if (O == Prec::F32) f64_to_f32(st, (const double*)b64.data, (float*)r->data, n5, act);
-  else apply5_full(st, Prec::F64, *r, b64, nullptr, vh, Ls, nullptr, act);
-  ctl_start(st, c, scal, n, x0_dev != nullptr);
-
-  // z = M r ; rho = <r, z> ; p = z ; t0 = M_phi p
-  if (pre) {
-    h->precondition(st, O, I, z, *r, nullptr, sp.inner_iters, p_z1, p_z2, act);
-    finish(st, p_z1, nullptr, nz, scal, FIN_RHO, 0, act);
-  } else {
-    dot2(st, O, r->data, r->data, nullptr, nreal, p_z1, nullptr, nbl, act);
-    finish(st, p_z1, nullptr, nbl, scal, FIN_RHO, 0, act);
   }
-  xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_TMP, h->mat(O, MAT_MPHI), vh, Ls, act);
 
-  auto iteration = [&]() {
+  // The start-up sequence of Alg. 1 for the slots whose join flag the host
+  // has set (the sources already packed into b64 by the caller): x = x0 or
+  // 0, |b|, r = b - A x, z = M r, rho = <r, z>, p = z, t0 = M_phi p.
+  void start(bool has_x0) {
+    zero_batched(st, p.data, bytesO, jn);
+    if (!has_x0) zero_batched(st, x64.data, bytes64, jn);
+    if (O == Prec::F32) zero_batched(st, x.data, bytesO, jn);
+    dot2(st, Prec::F64, b64.data, b64.data, nullptr, nreal, p_b, nullptr, nbl64, jn);
+    finish(st, p_b, nullptr, nbl64, scal, FIN_STORE, SLOT_TMP, jn);
+    ctl_init(st, c, scal, n, join);            // join becomes "joining and active"
+    zero_batched(st, x64.data, bytes64, bz);
+    if (has_x0) true_residual(jn);
+    else if (O == Prec::F32) f64_to_f32(st, (const double*)b64.data, (float*)r->data, n5, jn);
+    else apply5_full(st, Prec::F64, *r, b64, nullptr, vh, Ls, nullptr, jn);
+    ctl_start(st, c, scal, n, has_x0, join);
+    if (pre) {
+      h->precondition(st, O, I, z, *r, nullptr, sp.inner_iters, p_z1, p_z2, jn);
+      finish(st, p_z1, nullptr, nz, scal, FIN_RHO, 0, jn);
+    } else {
+      dot2(st, O, r->data, r->data, nullptr, nreal, p_z1, nullptr, nbl, jn);
+      finish(st, p_z1, nullptr, nbl, scal, FIN_RHO, 0, jn);
+    }
+    xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_TMP, h->mat(O, MAT_MPHI), vh, Ls, jn);
+  }
+
+  void iteration() {
     h->A_from_t0(st, O, q, p, t0, "Aout", p_pap, act);
     finish(st, p_pap, nullptr, bps_hop, scal, FIN_ALPHA, 0, act);
     cg_update(st, O, x.data, p.data, r->data, q.data, rold->data, nreal, scal, SLOT_ALPHA, p_upd, nbl, act);
@@ -1471,67 +1520,115 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
       finish(st, nullptr, nullptr, 0, scal, FIN_BETA_FR, SLOT_RR, act);
     }
     xpay_apply5(st, O, t0, p, pre ? z : *r, scal, SLOT_BETA, h->mat(O, MAT_MPHI), vh, Ls, act);
-  };
-  auto body = [&]() {
-    iteration();
-    iteration();
-  };
+  }
 
-  // the first pair runs eagerly (it sizes every workspace), then the pair is
-  // captured once and replayed; the host reads the active count of replay k
-  // while replay k + 1 runs
-  int64_t launched = 0;
-  const int64_t limit = (int64_t)sp.maxiter + 8;
-  auto post_flag = [&](int slot) {
-    HIPCHK(hipMemcpyAsync(h->h_flag + slot, c.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
-  };
-  hipEvent_t fev[2];
-  HIPCHK(hipEventCreateWithFlags(&fev[0], hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&fev[1], hipEventDisableTiming));
-  GraphGuard gg;
-  try {
-    body();
-    launched += 2;
-    post_flag(0);
-    HIPCHK(hipStreamSynchronize(st));
-    bool graph = use_graph;
-    if (h->h_flag[0] > 0) {
-      if (graph) {
-        // capture the pair; if the capture fails, nothing of it ran and the
-        // replays go eager (same kernels, same results)
-        std::shared_lock<std::shared_mutex> lk(g_capture_gate);
-        bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (ok) {
-          FieldPtr* const r_at = r;   // a body cut short leaves the r / r_old swap half done
-          FieldPtr* const ro_at = rold;
-          tl_capturing = true;
-          try {
-            body();
-          } catch (...) {
-            ok = false;
-          }
-          tl_capturing = false;
-          r = r_at;
-          rold = ro_at;
-          hipGraph_t g = nullptr;
-          const hipError_t ec = hipStreamEndCapture(st, &g);
-          ok = ok && ec == hipSuccess && g != nullptr;
-          if (ok) gg.g = g;
-          else if (g) (void)hipGraphDestroy(g);
-        }
-        lk.unlock();
-        if (ok) ok = hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0) == hipSuccess;
-        if (!ok) {
-          (void)hipGetLastError();
-          graph = false;
-          ++h->capture_fallbacks;
-        }
+  // Two iterations (the r / r_old swap returns to its start), then the count
+  // of active slots into the handle's pinned flag `slot`.  The first pair runs
+  // eagerly (it sizes every workspace); the second is captured and every
+  // later one replays the graph (eager if the capture failed: same kernels).
+  void run_pair(int flag_slot) {
+    if (graph_tried || !use_graph) {
+      if (graph) HIPCHK(hipGraphLaunch(gg.e, st));
+      else {
+        iteration();
+        iteration();
       }
+    } else if (!first_done) {
+      iteration();
+      iteration();
+      first_done = true;
+    } else {
+      graph_tried = true;
+      std::shared_lock<std::shared_mutex> lk(g_capture_gate);
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        FieldPtr* const r_at = r;   // a capture cut short leaves the swap half done
+        FieldPtr* const ro_at = rold;
+        tl_capturing = true;
+        try {
+          iteration();
+          iteration();
+        } catch (...) {
+          ok = false;
+        }
+        tl_capturing = false;
+        r = r_at;
+        rold = ro_at;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        ok = ok && ec == hipSuccess && g != nullptr;
+        if (ok) gg.g = g;
+        else if (g) (void)hipGraphDestroy(g);
+      }
+      lk.unlock();
+      if (ok) ok = hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0) == hipSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        ++h->capture_fallbacks;
+      }
+      graph = ok;
+      if (graph) HIPCHK(hipGraphLaunch(gg.e, st));   // nothing ran during the capture
+      else {
+        iteration();
+        iteration();
+      }
+    }
+    HIPCHK(hipMemcpyAsync(h->h_flag + flag_slot, c.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  bool first_done = false;
+
+  // statistics of slot i from the control arrays copied to the host
+  void stats_of(int i, const std::vector<int>& hi, const std::vector<double>& hd, float ms, double ms_pre,
+                mspcg_stats& S) const {
+    std::memset(&S, 0, sizeof(S));
+    const int status = hi[3 * n + i];
+    S.outer_iters = hi[4 * n + i];
+    S.reliable_updates = hi[5 * n + i];
+    S.inner_iters_total = pre ? hi[6 * n + i] * sp.inner_iters : 0;
+    const double bn = hd[i], rr = hd[2 * n + i];
+    const double rel = (hi[2 * n + i] || !(bn > 0)) ? 0.0 : std::sqrt(std::fabs(rr)) / bn;
+    S.true_rel_resid = rel;
+    S.iter_rel_resid = rel;
+    S.ms_total = ms;
+    S.ms_precond = ms_pre;
+    S.status = status == RHS_OK ? MSPCG_OK : status == RHS_BREAKDOWN ? MSPCG_ERR_BREAKDOWN : MSPCG_NOT_CONVERGED;
+  }
+  void download_ctl(std::vector<int>& hi, std::vector<double>& hd) {
+    hi.resize((size_t)8 * n + 1);
+    hd.resize((size_t)3 * n);
+    h->download(hi.data(), ci, hi.size() * sizeof(int), st);
+    h->download(hd.data(), cd, hd.size() * sizeof(double), st);
+  }
+};
+
+mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, double* x_dev, const double* x0_dev,
+                              hipStream_t st, mspcg_stats* stats) {
+  const int n = nrhs;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, st));
+  hipEvent_t fev[2] = {nullptr, nullptr};
+  std::unique_ptr<BatchEngine> E;
+  try {
+    E.reset(new BatchEngine(h, n, st, "s"));
+    BatchEngine& B = *E;
+    pack_field(st, B.b64, b_dev, B.vh, B.Ls, B.all);
+    if (x0_dev) pack_field(st, B.x64, x0_dev, B.vh, B.Ls, B.all);
+    fill_int(st, B.join, n, 1);
+    B.start(x0_dev != nullptr);
+    HIPCHK(hipEventCreateWithFlags(&fev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&fev[1], hipEventDisableTiming));
+    // the host reads the active count of pair k while pair k + 1 runs
+    const int64_t limit = (int64_t)B.sp.maxiter + 8;
+    int64_t launched = 0;
+    B.run_pair(0);
+    launched += 2;
+    HIPCHK(hipStreamSynchronize(st));
+    if (h->h_flag[0] > 0) {
       for (int64_t k = 0;; ++k) {
-        if (graph) HIPCHK(hipGraphLaunch(gg.e, st));
-        else body();
+        B.run_pair((int)(k & 1));
         launched += 2;
-        post_flag((int)(k & 1));
         HIPCHK(hipEventRecord(fev[k & 1], st));
         if (k > 0) {
           HIPCHK(hipEventSynchronize(fev[(k - 1) & 1]));
@@ -1549,27 +1646,24 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
     }
   } catch (...) {
     (void)hipStreamSynchronize(st);
-    (void)hipEventDestroy(fev[0]);
-    (void)hipEventDestroy(fev[1]);
+    for (hipEvent_t e : fev)
+      if (e) (void)hipEventDestroy(e);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     throw;
   }
-  (void)hipEventDestroy(fev[0]);
-  (void)hipEventDestroy(fev[1]);
-
-  unpack_field(st, x_dev, x64, vh, Ls, all);
+  for (hipEvent_t e : fev) (void)hipEventDestroy(e);
+  BatchEngine& B = *E;
+  unpack_field(st, x_dev, B.x64, B.vh, B.Ls, B.all);
   HIPCHK(hipEventRecord(e1, st));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-
-  std::vector<int> hi((size_t)8 * n + 1);
-  std::vector<double> hd((size_t)3 * n);
-  h->download(hi.data(), ci, hi.size() * sizeof(int), st);
-  h->download(hd.data(), cd, hd.size() * sizeof(double), st);
+  std::vector<int> hi;
+  std::vector<double> hd;
+  B.download_ctl(hi, hd);
   double ms_pre = 0;
   if (h->profiling) {
     for (auto& kv : h->ev_log)
@@ -1583,24 +1677,96 @@ mspcg_status solve_batch_impl(mspcg_ctx* h, int nrhs, const double* b_dev, doubl
     const int status = hi[3 * n + i];
     any_bd |= status == RHS_BREAKDOWN;
     any_nc |= status == RHS_NOT_CONVERGED || status == RHS_RUNNING;
-    if (!stats) continue;
-    mspcg_stats& S = stats[i];
-    std::memset(&S, 0, sizeof(S));
-    S.outer_iters = hi[4 * n + i];
-    S.reliable_updates = hi[5 * n + i];
-    S.inner_iters_total = pre ? hi[6 * n + i] * sp.inner_iters : 0;
-    const double bn = hd[i], rr = hd[2 * n + i];
-    const double rel = (hi[2 * n + i] || !(bn > 0)) ? 0.0 : std::sqrt(std::fabs(rr)) / bn;
-    S.true_rel_resid = rel;
-    S.iter_rel_resid = rel;
-    S.ms_total = ms;
-    S.ms_precond = ms_pre;
-    S.status = status == RHS_OK ? MSPCG_OK
-               : status == RHS_BREAKDOWN ? MSPCG_ERR_BREAKDOWN
-                                         : MSPCG_NOT_CONVERGED;
+    if (stats) B.stats_of(i, hi, hd, ms, ms_pre, stats[i]);
   }
   if (any_bd) return MSPCG_ERR_BREAKDOWN;
   return any_nc ? MSPCG_NOT_CONVERGED : MSPCG_OK;
+}
+
+// ---------------------------------------------------------------- continuous batching
+std::atomic<int> g_cb_sessions{0};   // open sessions of the process (mspcg_set_mfma waits for none)
+
+enum SlotState { SLOT_FREE = 0, SLOT_PENDING, SLOT_RUNNING, SLOT_DONE };
+
+struct CBSession {
+  mspcg_ctx* h;
+  hipStream_t st;
+  std::unique_ptr<BatchEngine> E;
+  struct Slot {
+    int state = SLOT_FREE;
+    const double* b = nullptr;
+    double* x = nullptr;
+    std::chrono::steady_clock::time_point t0;
+    mspcg_stats stats;
+  };
+  std::vector<Slot> slots;
+  int* h_status = nullptr;   // pinned copy of the per-slot RhsStatus
+  CBSession(mspcg_ctx* hh, int n, hipStream_t s) : h(hh), st(s), slots((size_t)n) {
+    E.reset(new BatchEngine(h, n, st, "cb"));
+    std::unique_lock<std::shared_mutex> lk(g_capture_gate);
+    HIPCHK(hipHostMalloc((void**)&h_status, (size_t)n * sizeof(int), hipHostMallocDefault));
+    ++g_cb_sessions;
+  }
+  ~CBSession() {
+    (void)hipStreamSynchronize(st);
+    {
+      std::unique_lock<std::shared_mutex> lk(g_capture_gate);
+      if (h_status) (void)hipHostFree(h_status);
+    }
+    --g_cb_sessions;
+  }
+
+  // pending slots start, one iteration pair runs, finished slots deliver x
+  void step(int* running, int* pending) {
+    BatchEngine& B = *E;
+    const int n = B.n;
+    std::vector<int> joining;
+    for (int i = 0; i < n; ++i)
+      if (slots[i].state == SLOT_PENDING) joining.push_back(i);
+    if (!joining.empty()) {
+      fill_int(st, B.join, n, 0);
+      for (int i : joining) {
+        pack_field(st, B.slot(B.b64, i), slots[i].b, B.vh, B.Ls, Batch());
+        fill_int(st, B.join + i, 1, 1);
+        slots[i].state = SLOT_RUNNING;
+        slots[i].t0 = std::chrono::steady_clock::now();
+      }
+      B.start(false);
+    }
+    bool any_running = false;
+    for (const Slot& sl : slots) any_running |= sl.state == SLOT_RUNNING;
+    if (any_running) B.run_pair(0);
+    HIPCHK(hipMemcpyAsync(h_status, B.c.status, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int> fin;
+    for (int i = 0; i < n; ++i)
+      if (slots[i].state == SLOT_RUNNING && h_status[i] != RHS_RUNNING) fin.push_back(i);
+    if (!fin.empty()) {
+      for (int i : fin) unpack_field(st, slots[i].x, B.slot(B.x64, i), B.vh, B.Ls, Batch());
+      std::vector<int> hi;
+      std::vector<double> hd;
+      B.download_ctl(hi, hd);   // synchronizes: the x of every finished slot is written
+      const auto now = std::chrono::steady_clock::now();
+      for (int i : fin) {
+        const float ms = (float)std::chrono::duration<double, std::milli>(now - slots[i].t0).count();
+        B.stats_of(i, hi, hd, ms, 0.0, slots[i].stats);
+        slots[i].state = SLOT_DONE;
+        slots[i].b = nullptr;
+        slots[i].x = nullptr;
+      }
+    }
+    int nr = 0, np = 0;
+    for (const Slot& sl : slots) {
+      nr += sl.state == SLOT_RUNNING;
+      np += sl.state == SLOT_PENDING;
+    }
+    if (running) *running = nr;
+    if (pending) *pending = np;
+  }
+};
+
+void no_session(const mspcg_ctx* h) {
+  if (h->cb) throw Error(MSPCG_ERR_INVALID_ARG, "a continuous-batching session is open on this handle");
 }
 
 // --------------------------------------------------------------------------
@@ -1736,7 +1902,7 @@ int64_t estimate_solve_bytes(const mspcg_ctx* h, int nrhs) {
   }
   n += parts * 8;
   n *= nrhs;
-  n += (int64_t)(8 * nrhs + 1) * 4 + (int64_t)3 * nrhs * 8 + (int64_t)nrhs * SLOT_COUNT * 8;
+  n += round16((int64_t)(8 * nrhs + 1) * 4) + (int64_t)3 * nrhs * 8 + (int64_t)nrhs * 4 + (int64_t)nrhs * SLOT_COUNT * 8;
   // matrices and tables
   n += (int64_t)h->mats64.n + (int64_t)h->mats32.n;
   for (const DevBuf* d : {&h->tb_origin, &h->tb_cC, &h->tb_cN1, &h->tb_cN2, &h->tb_nbr1, &h->tb_nbr2, &h->tb_nbr3,
@@ -1837,6 +2003,7 @@ mspcg_status mspcg_destroy(mspcg_t h) {
 mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
   return guarded([&]() -> mspcg_status {
     if (!h || !U) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     h->ensure_hip();
     hipStream_t st = h->stream;
     const int64_t V = 2 * h->lat.vh;
@@ -1862,6 +2029,7 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U) {
 mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double M5, double mf) {
   return guarded([&]() -> mspcg_status {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    no_session(h);
     if (Ls < 2 || Ls > 32) throw Error(MSPCG_ERR_INVALID_ARG, "Ls must be in [2, 32]");
     if (!std::isfinite(b) || !std::isfinite(c) || !std::isfinite(M5) || !std::isfinite(mf))
       throw Error(MSPCG_ERR_INVALID_ARG, "non-finite Mobius parameter");
@@ -1894,6 +2062,7 @@ mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double 
 mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
   return guarded([&]() -> mspcg_status {
     if (!h || !sub) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     int s[4] = {sub[0], sub[1], sub[2], sub[3]};
     std::string why;
     if (!tiling_valid(h->dims, s, why)) throw Error(MSPCG_ERR_BAD_TILING, why);
@@ -1947,6 +2116,7 @@ mspcg_status mspcg_set_subdomains(mspcg_t h, const int32_t sub[4]) {
 mspcg_status mspcg_set_solver(mspcg_t h, const mspcg_solver_params* p) {
   return guarded([&]() -> mspcg_status {
     if (!h || !p) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (!(p->tol > 0) || p->maxiter < 1 || p->inner_iters < 0 || p->inner_iters > 1000)
       throw Error(MSPCG_ERR_INVALID_ARG, "tol > 0, maxiter >= 1, 0 <= inner_iters <= 1000 required");
     if (p->outer_prec != MSPCG_FP64 && p->outer_prec != MSPCG_FP32)
@@ -1966,6 +2136,7 @@ mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const dou
                                 mspcg_stats* st) {
   return guarded([&]() -> mspcg_status {
     if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
@@ -1977,6 +2148,7 @@ mspcg_status mspcg_solve_device(mspcg_t h, const double* b, double* x, const dou
 mspcg_status mspcg_solve(mspcg_t h, const double* b, double* x, const double* x0, mspcg_stats* st) {
   return guarded([&]() -> mspcg_status {
     if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
@@ -1999,6 +2171,7 @@ mspcg_status mspcg_solve_full_device(mspcg_t h, const double* phi, double* psi, 
                                      double* full_rel_resid) {
   return guarded([&]() -> mspcg_status {
     if (!h || !phi || !psi) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
     h->ensure_hip();
@@ -2011,6 +2184,7 @@ mspcg_status mspcg_solve_batch_device(mspcg_t h, int32_t nrhs, const double* b, 
                                       void* hip_stream, mspcg_stats* st) {
   return guarded([&]() -> mspcg_status {
     if (!h || !b || !x) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
@@ -2023,6 +2197,7 @@ mspcg_status mspcg_solve_batch_device(mspcg_t h, int32_t nrhs, const double* b, 
 mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src) {
   return guarded([&]() -> mspcg_status {
     if (!h || !src) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    no_session(h);
     if (!src->have_gauge) throw Error(MSPCG_ERR_NO_GAUGE, "source handle has no gauge field");
     for (int m = 0; m < 4; ++m)
       if (h->dims[m] != src->dims[m]) throw Error(MSPCG_ERR_INVALID_ARG, "lattice extents differ");
@@ -2038,6 +2213,7 @@ mspcg_status mspcg_share_gauge(mspcg_t h, mspcg_t src) {
 mspcg_status mspcg_set_reduced(mspcg_t h, int32_t Lhat, double b_hat, double c_hat, double mu, const double* T) {
   return guarded([&]() -> mspcg_status {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    no_session(h);
     if (Lhat == 0) {
       if (h->hip_ready) HIPCHK(hipStreamSynchronize(h->stream));
       h->Lh = 0;
@@ -2079,6 +2255,7 @@ mspcg_status mspcg_get_reduced(mspcg_t h, int32_t* Lhat, double* T) {
 mspcg_status mspcg_reduced_loss(mspcg_t h, int32_t nvec, const double* v, double* chi2, double* grad) {
   return guarded([&]() -> mspcg_status {
     if (!h || !v || !chi2) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (nvec < 1) throw Error(MSPCG_ERR_INVALID_ARG, "nvec must be >= 1");
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
@@ -2096,6 +2273,7 @@ mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32
                                  double* history) {
   return guarded([&]() -> mspcg_status {
     if (!h || !v) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (nvec < 1 || iters < 0) throw Error(MSPCG_ERR_INVALID_ARG, "nvec must be >= 1 and iters >= 0");
     if (!std::isfinite(momentum)) throw Error(MSPCG_ERR_INVALID_ARG, "non-finite momentum");
     need_state(h);
@@ -2111,6 +2289,9 @@ mspcg_status mspcg_train_reduced(mspcg_t h, int32_t nvec, const double* v, int32
 mspcg_status mspcg_set_mfma(int32_t on) {
   return guarded([&]() -> mspcg_status {
     std::unique_lock<std::shared_mutex> lk(g_engine_gate);
+    if (g_cb_sessions.load() > 0)
+      throw Error(MSPCG_ERR_INVALID_ARG, "continuous-batching sessions are open (their launches are sized for "
+                                         "the current epilogue engine)");
     set_mfma_epilogue(on != 0);
     return MSPCG_OK;
   });
@@ -2128,6 +2309,7 @@ mspcg_status mspcg_set_log(mspcg_t h, int32_t every) {
 mspcg_status mspcg_set_graphs(mspcg_t h, int32_t on) {
   return guarded([&]() -> mspcg_status {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    no_session(h);
     h->graphs = on != 0;
     return MSPCG_OK;
   });
@@ -2147,6 +2329,7 @@ mspcg_status mspcg_footprint(mspcg_t h, int32_t nrhs, int64_t* estimate, int64_t
 mspcg_status mspcg_autotune(mspcg_t h, int32_t nrhs) {
   return guarded([&]() -> mspcg_status {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    no_session(h);
     if (nrhs < 1 || nrhs > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
@@ -2168,6 +2351,7 @@ static std::tuple<int, int, int> sched_key(const mspcg_t h, int32_t kind, int32_
 mspcg_status mspcg_set_schedule(mspcg_t h, int32_t kind, int32_t nrhs, int32_t order, int32_t xcd, int32_t tchunk) {
   return guarded([&]() -> mspcg_status {
     if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    no_session(h);
     if (order < 0 || order > 1 || xcd < 0 || xcd > 1 || tchunk < 0 || tchunk > 4)
       throw Error(MSPCG_ERR_INVALID_ARG, "order and xcd must be 0 or 1, tchunk in [0, 4]");
     const auto key = sched_key(h, kind, nrhs);
@@ -2209,6 +2393,7 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
                                 void* hip_stream) {
   return guarded([&]() -> mspcg_status {
     if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
@@ -2224,6 +2409,7 @@ mspcg_status mspcg_apply_device_noalloc(mspcg_t h, int32_t op, mspcg_prec prec, 
                                         void* hip_stream) {
   return guarded([&]() -> mspcg_status {
     if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
@@ -2255,6 +2441,7 @@ mspcg_status mspcg_apply_device_noalloc(mspcg_t h, int32_t op, mspcg_prec prec, 
 mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out) {
   return guarded([&]() -> mspcg_status {
     if (!h || !in || !out) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    no_session(h);
     if (op < MSPCG_OP_DSLASH_EO || op > MSPCG_OP_STORE) throw Error(MSPCG_ERR_INVALID_ARG, "unknown operator");
     const Prec P = to_prec(prec);
     need_state(h);
@@ -2268,6 +2455,92 @@ mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* i
     h->upload(di.p, in, bytes, h->stream);
     apply_impl(h, op, P, di.as<double>(), dout.as<double>(), h->stream);
     h->download(out, dout.p, bytes, h->stream);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_get_history(mspcg_t h, double* out, double* pap, int32_t max, int32_t* count) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !count || (max > 0 && !out)) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (max < 0) throw Error(MSPCG_ERR_INVALID_ARG, "max must be >= 0");
+    const int n = (int)std::min<size_t>((size_t)max, h->history.size());
+    for (int i = 0; i < n; ++i) out[i] = h->history[(size_t)i];
+    if (pap)
+      for (int i = 0; i < n; ++i) pap[i] = (size_t)i < h->history_pap.size() ? h->history_pap[(size_t)i] : 0.0;
+    *count = (int32_t)h->history.size();
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_cb_open(mspcg_t h, int32_t slots, void* hip_stream) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (slots < 1 || slots > 1024) throw Error(MSPCG_ERR_INVALID_ARG, "slots must be in [1, 1024]");
+    no_session(h);
+    need_state(h);
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
+    h->ensure_hip();
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->stream;
+    h->cb = std::make_shared<CBSession>(h, slots, s);
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_cb_submit(mspcg_t h, const double* b, double* x, int32_t* slot) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !b || !x || !slot) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (!h->cb) throw Error(MSPCG_ERR_INVALID_ARG, "no continuous-batching session is open");
+    *slot = -1;
+    auto& sl = h->cb->slots;
+    for (size_t i = 0; i < sl.size(); ++i)
+      if (sl[i].state == SLOT_FREE) {
+        sl[i].state = SLOT_PENDING;
+        sl[i].b = b;
+        sl[i].x = x;
+        *slot = (int32_t)i;
+        return MSPCG_OK;
+      }
+    g_last_error = "every slot is taken";
+    return MSPCG_BUSY;
+  });
+}
+
+mspcg_status mspcg_cb_step(mspcg_t h, int32_t* running, int32_t* pending) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (!h->cb) throw Error(MSPCG_ERR_INVALID_ARG, "no continuous-batching session is open");
+    std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
+    HIPCHK(hipSetDevice(h->device));
+    int r = 0, p = 0;
+    h->cb->step(&r, &p);
+    if (running) *running = r;
+    if (pending) *pending = p;
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_cb_poll(mspcg_t h, int32_t slot, int32_t* done, mspcg_stats* st) {
+  return guarded([&]() -> mspcg_status {
+    if (!h || !done) throw Error(MSPCG_ERR_INVALID_ARG, "null argument");
+    if (!h->cb) throw Error(MSPCG_ERR_INVALID_ARG, "no continuous-batching session is open");
+    auto& sl = h->cb->slots;
+    if (slot < 0 || (size_t)slot >= sl.size()) throw Error(MSPCG_ERR_INVALID_ARG, "slot out of range");
+    *done = sl[slot].state == SLOT_DONE ? 1 : 0;
+    if (*done) {
+      if (st) *st = sl[slot].stats;
+      sl[slot].state = SLOT_FREE;
+    }
+    return MSPCG_OK;
+  });
+}
+
+mspcg_status mspcg_cb_close(mspcg_t h) {
+  return guarded([&]() -> mspcg_status {
+    if (!h) throw Error(MSPCG_ERR_INVALID_ARG, "null handle");
+    if (h->cb) {
+      HIPCHK(hipSetDevice(h->device));
+      h->cb.reset();
+    }
     return MSPCG_OK;
   });
 }

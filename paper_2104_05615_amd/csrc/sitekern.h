@@ -819,7 +819,10 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
     }
   }
   T pv[24];
-  if (early && dot_partial) load_site(dotf, valid ? (uint32_t)r.out5 : 0u, pv);
+  // the fused dot <p, A p> belongs to the last hop of A (adjoint, with a
+  // centre field): only those instances hold its field in registers
+  constexpr bool DOT = DAG && HASW;
+  if (DOT && early && dot_partial) load_site(dotf, valid ? (uint32_t)r.out5 : 0u, pv);
 
   if constexpr (MF) {
     constexpr bool HO = UsesMfma<S>::half_ops;
@@ -981,7 +984,7 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
       }
     }
   }
-  if (dot_partial) {
+  if (DOT && dot_partial) {
     T loc = 0;
     if (valid) {
       if (!early) load_site(dotf, r.out5, pv);

@@ -175,3 +175,96 @@ def test_batch_warm_start_and_uneven_convergence():
         x1, s1 = s.solve(b[i], x0=x0[i])
         assert s1.outer_iters == st2[i].outer_iters and np.array_equal(x1, xw[i])
         assert oracle_resid(op, b[i], xw[i]) < 2e-10
+
+
+# ---------------------------------------------------------------- continuous batching
+
+@pytest.mark.parametrize("outer,inner,pre,beta", [("fp32", "fp16", True, "PR"), ("fp64", "fp64", False, "FR")])
+def test_continuous_batching_session_reproduces_each_source_alone(outer, inner, pre, beta):
+    """A session of 3 slots: sources enter while others iterate (two at the
+    start, a third after a few steps, two more as slots free up, one
+    refused while every slot is taken) and each leaves with the solution and
+    counts of its own one-RHS batched solve, bit for bit; a zero source
+    finishes at once with x = 0.  The oracle checks two residuals."""
+    import torch
+    dims, Ls, sub = (8, 4, 4, 4), 4, (4, 4, 4, 4)
+    s, op = make(dims, Ls, 0.05, sub)
+    s.set_solver(tol=1e-10, maxiter=3000, inner_iters=3, inner_prec=inner, outer_prec=outer,
+                 use_precond=pre, beta_rule=beta)
+    bs = [W.gaussian_source(dims, Ls, 900 + k) for k in range(5)] + [np.zeros_like(W.gaussian_source(dims, Ls, 1))]
+    ref = []
+    for b in bs:
+        st, stats, xs = batch_solve(s, [b])
+        ref.append((stats[0], xs[0]))
+    bt = [dev([b]) for b in bs]
+    xt = [torch.full_like(b, float("nan")) for b in bt]
+    torch.cuda.synchronize()
+    say(f"[gpu] continuous batching outer={outer} inner={inner} precond={pre}")
+    s.cb_open(3)
+    try:
+        slot_of, got = {}, {}
+        queue = list(range(len(bs)))
+
+        def submit_next():
+            if not queue:
+                return False
+            i = queue[0]
+            k = s.cb_submit(bt[i].data_ptr(), xt[i].data_ptr())
+            if k is None:
+                return False
+            slot_of[k] = i
+            queue.pop(0)
+            return True
+
+        submit_next()
+        submit_next()
+        steps, refused = 0, 0
+        while len(got) < len(bs):
+            if steps == 3 or (steps > 3 and steps % 2 == 0):
+                while submit_next():
+                    pass
+                if queue and s.cb_submit(bt[queue[0]].data_ptr(), xt[queue[0]].data_ptr()) is None:
+                    refused += 1
+            running, pending = s.cb_step()
+            steps += 1
+            for k in list(slot_of):
+                st = s.cb_poll(k)
+                if st is not None:
+                    got[slot_of.pop(k)] = st
+            assert steps < 4000
+        torch.cuda.synchronize()
+    finally:
+        s.cb_close()
+    say(f"      {steps} steps, {refused} submissions refused while every slot was taken")
+    assert refused >= 1
+    for i, (rs, rx) in enumerate(ref):
+        g = got[i]
+        x = xt[i].cpu().numpy().view(np.complex128).reshape(bs[i].shape)
+        assert g.status == rs.status == 0, (i, g, rs)
+        assert (g.outer_iters, g.reliable_updates) == (rs.outer_iters, rs.reliable_updates), (i, g, rs)
+        assert np.array_equal(x, rx), i
+    assert got[5].outer_iters == 0 and np.all(xt[5].cpu().numpy() == 0)
+    for i in (0, 3):
+        x = xt[i].cpu().numpy().view(np.complex128).reshape(bs[i].shape)
+        assert oracle_resid(op, bs[i], x) < 2e-10
+
+
+def test_continuous_batching_session_refuses_other_calls():
+    from paper_2104_05615_amd import MSPCGError
+    import paper_2104_05615_amd as M
+    dims, Ls, sub = (8, 4, 4, 4), 4, (4, 4, 4, 4)
+    s, op = make(dims, Ls, 0.05, sub)
+    s.set_solver(tol=1e-10, maxiter=100, inner_iters=2)
+    s.cb_open(2)
+    try:
+        for call in (lambda: s.set_solver(tol=1e-8), lambda: s.solve(W.gaussian_source(dims, Ls, 3)),
+                     lambda: s.apply("A", "fp32", W.gaussian_source(dims, Ls, 4)), lambda: s.cb_open(2),
+                     lambda: M._check(M.mspcg_set_mfma(0))):
+            with pytest.raises(MSPCGError) as e:
+                call()
+            assert e.value.status == -1
+    finally:
+        s.cb_close()
+    s.set_solver(tol=1e-10, maxiter=2000, inner_iters=2)   # usable again after the session
+    x, st = s.solve(W.gaussian_source(dims, Ls, 5))
+    assert st.status == 0

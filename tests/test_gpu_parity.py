@@ -1,15 +1,31 @@
 """GPU parity: every operator of the C ABI against the FP64 oracle.
 
 Inputs are seeded (workloads/); the oracle computes the same operator from
-its definition on the CPU.  Tolerances (relative L2 error of the output):
-FP64 1e-12, FP32 1e-6, FP16 3e-3 (a single hop 1.5e-3), BF16 3e-2 -- the FP32
-and FP16 bounds are the ones fixed for operator applications; BF16 has 3
-fewer mantissa bits than FP16 and gets 8x the FP16 bound.  INT8 rounds each
-real to a step of m/127 (m the site's largest magnitude): one store of a
-Gaussian field costs a relative error of about 5e-3 against FP16's 1.7e-4
-and BF16's 1.4e-3 (uniform rounding, measured by the oracle's storage
-pins); its bounds keep the same multiple of that one-store error as the
-BF16 bounds: 4.5e-2 for a hop, 1e-1 for a composite operator.
+its definition on the CPU.  Two measures are checked for every output: the
+relative L2 error of the whole field, and the largest error of one 5D site
+(its 24 reals) relative to the largest site of the reference, so that a
+small wrong region (a face, a subdomain, one site block) cannot hide under a
+whole-field norm.  Bounds against the exact operator: FP64 1e-12, FP32 1e-6,
+FP16 3e-3 (a single hop 1.5e-3), BF16 3e-2, INT8 1e-1 -- the FP32 and FP16
+bounds are the ones fixed for operator applications; BF16 has 3 fewer
+mantissa bits than FP16 and gets 8x the FP16 bound; INT8 rounds each real to
+a step of m/127 (m the site's largest magnitude), about 5e-3 per store of a
+Gaussian field, and keeps the same multiple of its one-store error.
+
+The local operator and the preconditioner in the 16- and 8-bit formats get
+bounds from the error the format itself causes on the test's input: the
+oracle's model of the format (``oracle.local_operator_stored`` /
+``oracle.inner_cg_stored``: every field a kernel writes stored in the format,
+FP16 links) against the exact operator, times 2.5, plus an allowance for the
+fifth-dimension epilogue's FP16 operands (each value within 2^-12 of its site
+column's largest, which the model leaves out).  Each test asserts that this
+bound is well below the share of the snake terms (Sec. 2.3, eq. diri) in that
+operator on that tiling, measured with the oracle's per-hop truncated
+operator: an implementation that dropped them could not pass.  (The model is
+not compared with the GPU directly: the epilogue's rounding, relative to a
+site column's largest value, moves the small fifth-dimension slices of a
+site by more than one step of the 8-bit and BF16 formats, so those
+rounding decisions are independent of the model's.)
 """
 import sys
 
@@ -42,6 +58,31 @@ def say(*a):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def site_rel(a, b):
+    """max over 5D sites of |a - b| over the site, relative to the largest
+    site norm of b (a site is the 4 x 3 complex components)"""
+    d = np.linalg.norm((a - b).reshape(-1, 12), axis=1)
+    return float(d.max() / np.linalg.norm(b.reshape(-1, 12), axis=1).max())
+
+
+# the largest single-site error allowed, as a multiple of the field's L2 bound
+SITE = 4.0
+# allowance for the epilogue's FP16 operands (measured ~3e-4 for one A_s,
+# ~5e-4 for the k = 3 preconditioner, FP16 storage)
+EPI = {"A_sub": 1e-3, "precond": 2e-3}
+
+
+def format_bound(kind, model_err):
+    """2.5 x the format's own error on the input, plus the epilogue allowance."""
+    return 2.5 * model_err + EPI[kind]
+
+
+def check(got, ref, tol, what):
+    e, es = rel(got, ref), site_rel(got, ref)
+    assert e < tol and es < SITE * tol, (what, e, es, tol)
+    return e, es
 
 
 def rand_field(Ls, vh, seed):
@@ -79,8 +120,7 @@ def test_dslash_parity(dims, Ls, prec):
         say(f"[gpu] {name} {prec} dims={dims} Ls={Ls}")
         got = s.apply(name, prec, psi)
         ref = oracle.wilson_hop(U, psi, par, dagger=dag)
-        e = rel(got, ref)
-        assert e < TOL_HOP[prec], (name, prec, e)
+        check(got, ref, TOL_HOP[prec], (name, prec))
 
 
 @pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 8), ((4, 2, 6, 4), 12), ((6, 4, 2, 8), 5)])
@@ -92,8 +132,7 @@ def test_fifth_dimension_ops(dims, Ls, prec):
     for name, M in (("m5", op.M5op), ("m5inv", op.M5inv), ("mphi", op.Mphi)):
         say(f"[gpu] {name} {prec} dims={dims} Ls={Ls}")
         got = s.apply(name, prec, psi)
-        e = rel(got, oracle.apply5(M, psi))
-        assert e < tol, (name, prec, e)
+        check(got, oracle.apply5(M, psi), tol, (name, prec))
 
 
 # ---------------------------------------------------------------- D, D^dag, A
@@ -106,8 +145,7 @@ def test_schur_and_normal_operator(dims, Ls, prec):
     for name, f in (("D", op.D), ("Ddag", op.Ddag), ("A", op.A)):
         say(f"[gpu] {name} {prec} dims={dims} Ls={Ls}")
         got = s.apply(name, prec, psi)
-        e = rel(got, f(psi))
-        assert e < TOL_A[prec], (name, prec, e)
+        check(got, f(psi), TOL_A[prec], (name, prec))
 
 
 @pytest.mark.parametrize("dims,Ls", [((4, 4, 4, 4), 4), ((6, 4, 2, 8), 5)])
@@ -157,6 +195,40 @@ SUBS = [
 ]
 
 
+_share = {}
+
+
+def snake_share(dims, Ls, sub, what):
+    """Share of the snake terms: the relative change of A_s r_s (or of the
+    k = 3 preconditioner) when the Dirichlet cut is applied to every hop
+    instead of to the whole operator (eq. diri), on the tests' inputs."""
+    key = (dims, Ls, sub, what)
+    if key not in _share:
+        import oracle.dwf as D
+        s, op, U = setup(dims, Ls, sub=sub)
+        til = oracle.Tiling(dims, sub)
+        if what == "A_sub":
+            vs = til.restrict(rand_field(Ls, op.vh, 9))
+            _share[key] = rel(oracle.truncated_local_operator(op, til, vs), oracle.local_operator(op, til, vs))
+        else:
+            r = rand_field(Ls, op.vh, 13)
+            z = oracle.inner_cg(op, til, r, 3)
+            real = D.local_operator
+            D.local_operator = lambda o, t, v, subset=None, batch=8, padded=False: \
+                D.truncated_local_operator(o, t, v, subset=subset)
+            try:
+                zt = oracle.inner_cg(op, til, r, 3)
+            finally:
+                D.local_operator = real
+            _share[key] = rel(zt, z)
+    return _share[key]
+
+
+def model_op(op, prec):
+    """The oracle operator on the links as the 16- and 8-bit kernels hold them."""
+    return oracle.MobiusDWF(oracle.stored_links(op.U, prec), op.Ls, op.b, op.c, op.M5, op.mf)
+
+
 @pytest.mark.parametrize("dims,Ls,sub", SUBS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16", "int8"])
 def test_local_operator_parity(dims, Ls, sub, prec):
@@ -165,9 +237,19 @@ def test_local_operator_parity(dims, Ls, sub, prec):
     r = rand_field(Ls, op.vh, 9)
     say(f"[gpu] A_sub {prec} dims={dims} sub={sub} Ls={Ls}")
     got = s.apply("A_sub", prec, r)
-    ref = til.prolong(oracle.local_operator(op, til, til.restrict(r)), op.vh)
-    e = rel(got, ref)
-    assert e < TOL_A[prec], (prec, e)
+    vs = til.restrict(r)
+    ex = oracle.local_operator(op, til, vs)
+    ref = til.prolong(ex, op.vh)
+    tol = TOL_A[prec]
+    if prec in ("fp16", "bf16", "int8"):
+        share = snake_share(dims, Ls, sub, "A_sub")
+        model_err = rel(oracle.local_operator_stored(model_op(op, prec), til, vs, prec), ex)
+        tol = min(tol, format_bound("A_sub", model_err))
+        assert tol < share / 2.5, (tol, share)
+    e, es = check(got, ref, tol, prec)
+    if prec in ("fp16", "bf16", "int8"):
+        say(f"      {e:.2e} (worst site {es:.2e}), bound {tol:.2e} (format alone {model_err:.2e}), "
+            f"snake share {share:.3f}")
 
 
 @pytest.mark.parametrize("dims,Ls,sub", SUBS)
@@ -175,10 +257,11 @@ def test_local_operator_parity(dims, Ls, sub, prec):
                                       ("int8", 5e-1)])
 def test_preconditioner_parity(dims, Ls, sub, prec, tol):
     """k = 3 inner CG steps per subdomain.  The inner CG is nonlinear in its
-    input; low-precision storage perturbs its scalars, so FP16/BF16/INT8 get
-    a looser bound than a single operator application (INT8's catches a
-    wrong encoding, not the preconditioner's quality: the INT8 solve test
-    checks that)."""
+    input; against the exact preconditioner low-precision storage perturbs
+    its scalars, so FP16/BF16/INT8 get a looser bound there than a single
+    operator application; the 16- and 8-bit formats are held to 2.5x the
+    error the format itself causes (the oracle's model), far below the
+    snake terms' share of the preconditioner."""
     s, op, U = setup(dims, Ls, sub=sub)
     s.set_solver(inner_iters=3)
     til = oracle.Tiling(dims, sub)
@@ -186,8 +269,16 @@ def test_preconditioner_parity(dims, Ls, sub, prec, tol):
     say(f"[gpu] precond {prec} dims={dims} sub={sub} Ls={Ls}")
     got = s.apply("precond", prec, r)
     ref = oracle.precondition(op, til, r, 3)
-    e = rel(got, ref)
-    assert e < tol, (prec, e)
+    if prec in ("fp16", "bf16", "int8"):
+        share = snake_share(dims, Ls, sub, "precond")
+        model = til.prolong(oracle.inner_cg_stored(model_op(op, prec), til, r, 3, prec), op.vh)
+        model_err = rel(model, ref)
+        tol = min(tol, format_bound("precond", model_err))
+        assert tol < share / 2.5, (tol, share)
+    e, es = check(got, ref, tol, prec)
+    if prec in ("fp16", "bf16", "int8"):
+        say(f"      {e:.2e} (worst site {es:.2e}), bound {tol:.2e} (format alone {model_err:.2e}), "
+            f"snake share {share:.3f}")
 
 
 def test_preconditioner_locality():
@@ -277,6 +368,69 @@ def test_c1_fp64_mspcg_matches_oracle_solution():
     say(f"      sampled relative error {rms_rel:.2e} (bound kappa*tol = {ref['kappa'] * tol:.2e})")
     assert rms_rel < 2 * ref["kappa"] * tol
     assert st.outer_iters < ref["iters"]
+
+
+def test_c1_fp64_residual_history_matches_the_oracle():
+    """The iterated relative residual |r_k| / |b| of the first 20 outer
+    iterations (the quantity of Fig. residual-rbc and Fig. residual-cal) of
+    the FP64 MSPCG solve on the 8^4 x Ls8 workload agrees with the oracle's
+    MSPCG (same tiling, k = 5, PR beta) to 1e-8 relative; both start at 1."""
+    from workloads.configs import CONFIGS
+    c = CONFIGS["c1"]
+    s, op, U = setup(c.dims, c.Ls, mf=c.mf, eps=c.eps, seed=c.gauge_seed, sub=c.sub)
+    b = W.gaussian_source(c.dims, c.Ls, c.src_seed)
+    s.set_solver(tol=1e-10, maxiter=2000, inner_iters=c.inner_iters, inner_prec="fp64", outer_prec="fp64")
+    say("[gpu] c1 mspcg fp64: residual history")
+    x, st = s.solve(b)
+    h = s.history()
+    assert st.status == 0 and len(h) == st.outer_iters + 1
+    til = oracle.Tiling(c.dims, c.sub)
+    _, info = oracle.mspcg(op, til, b, c.inner_iters, 1e-10, 20)
+    ref = np.array(info.history[:21])
+    got = h[:21]
+    d = np.max(np.abs(got - ref) / ref)
+    say(f"      first 21 residuals: max relative difference {d:.2e} (|r_20|/|b| = {ref[-1]:.3e})")
+    assert got[0] == 1.0 and ref[0] == 1.0
+    assert d < 1e-8, d
+
+
+def lanczos_extremes(alphas, betas):
+    """Extreme eigenvalues of the Lanczos matrix of CG (diagonal
+    1/alpha_i + beta_{i-1}/alpha_{i-1}, off-diagonal sqrt(beta_i)/alpha_i)."""
+    n = len(alphas)
+    T = np.zeros((n, n))
+    for i in range(n):
+        T[i, i] = 1 / alphas[i] + (betas[i - 1] / alphas[i - 1] if i > 0 else 0.0)
+        if i + 1 < n:
+            T[i, i + 1] = T[i + 1, i] = np.sqrt(betas[i]) / alphas[i]
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1])
+
+
+def test_c1_extreme_eigenvalues_from_the_cg_coefficients():
+    """The FP64 plain CG solve to 1e-12 on the 8^4 x Ls8 workload gives,
+    through the exported residuals and <p, A p>, the CG coefficients whose
+    Lanczos matrix estimates the extreme eigenvalues of A; they agree with
+    the oracle's estimate from its own CG (tests/golden/reference_c1.json)."""
+    import json
+    import os
+    from workloads.configs import CONFIGS
+    c = CONFIGS["c1"]
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "reference_c1.json")))
+    s, op, U = setup(c.dims, c.Ls, mf=c.mf, eps=c.eps, seed=c.gauge_seed, sub=c.sub)
+    b = W.gaussian_source(c.dims, c.Ls, c.src_seed)
+    s.set_solver(tol=1e-12, maxiter=2000, outer_prec="fp64", use_precond=False, beta_rule="FR", reliable_delta=0.0)
+    say("[gpu] c1 plain CG fp64 to 1e-12: Lanczos extremes")
+    x, st = s.solve(b)
+    h, pap = s.history(pap=True)
+    rho = h ** 2
+    alphas = rho[:-1] / pap
+    betas = rho[1:-1] / rho[:-2]
+    lmin, lmax = lanczos_extremes(alphas, betas)
+    say(f"      {st.outer_iters} iterations (oracle {ref['iters']}), lambda_min {lmin:.6e} ({ref['lambda_min']:.6e}), "
+        f"lambda_max {lmax:.6e} ({ref['lambda_max']:.6e})")
+    assert st.status == 0 and abs(st.outer_iters - ref["iters"]) <= 2
+    assert abs(lmin / ref["lambda_min"] - 1) < 1e-6 and abs(lmax / ref["lambda_max"] - 1) < 1e-6
 
 
 def test_gauge_invariance_of_solve():
@@ -382,12 +536,10 @@ def test_vector_alu_epilogue_paths(prec, Ls, mfma):
         s.set_mobius(Ls, 1.5, 0.5, 1.8, 0.1)
         s.set_subdomains(sub)
         say(f"[gpu] VALU epilogue {prec} Ls={Ls} mfma={mfma}")
-        e = rel(s.apply("A", prec, psi), op.A(psi))
-        assert e < TOL_A[prec], ("A", prec, e)
+        check(s.apply("A", prec, psi), op.A(psi), TOL_A[prec], ("A", prec))
         got = s.apply("A_sub", prec, psi)
         ref = til.prolong(oracle.local_operator(op, til, til.restrict(psi)), op.vh)
-        e = rel(got, ref)
-        assert e < TOL_A[prec], ("A_sub", prec, e)
+        check(got, ref, TOL_A[prec], ("A_sub", prec))
         s.close()
     finally:
         M.mspcg_set_mfma(1)

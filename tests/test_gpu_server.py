@@ -1,11 +1,15 @@
-"""GPU: the request loop (mspcg_server_*) -- resident fields and contexts,
-admission by device footprint, concurrent requests on separate streams.
+"""GPU: the request loop (mspcg_server_*) -- resident fields, admission by
+device footprint, and its two ways of running requests: continuous batching
+(the right-hand sides of one shape share the slots of one running batched
+solve and enter it while others iterate; shapes run concurrently) and one
+batched solve per request on its own stream.
 
-A request's arithmetic does not depend on what runs beside it, so every
-result must be the same alone (one request at a time) and in the mix (up
-to four requests in flight): same iteration counts and the same solution,
-bit for bit -- inside the stated tolerance by a wide margin.  The oracle
-checks the residuals.
+A right-hand side's arithmetic does not depend on what runs beside it, so
+every result must be the same alone (one request at a time, one batched
+solve per request) and in the mix (all requests at once, continuously
+batched, and as concurrent per-request solves): same iteration counts and
+the same solution, bit for bit -- inside the stated tolerance by a wide
+margin.  The oracle checks the residuals.
 """
 import sys
 
@@ -46,10 +50,11 @@ def sources(i, dims, Ls, nrhs):
     return [W.gaussian_source(dims, Ls, 700 + 10 * i + k) for k in range(nrhs)]
 
 
-def run(max_inflight, budget=64 << 30, order=None):
+def run(max_inflight, budget=64 << 30, order=None, mode="batching", slots=3):
     import torch
     from paper_2104_05615_amd import Server
     srv = Server(0, budget, max_inflight)
+    srv.set_mode(mode, slots)
     ids = {k: srv.add_field(d, W.gauge_field(d, eps, seed)) for k, (d, eps, seed) in FIELDS.items()}
     bufs, out = [], {}
     tickets = []
@@ -81,23 +86,30 @@ def run(max_inflight, budget=64 << 30, order=None):
 
 
 def test_server_results_same_alone_and_in_the_mix():
-    say("[gpu] server: requests one at a time")
-    alone, info1 = run(1)
+    say("[gpu] server: requests one at a time, one batched solve each")
+    alone, info1 = run(1, mode="contexts")
     say(f"      {info1}")
     assert info1["peak_inflight"] == 1
     assert info1["contexts"] < len(REQUESTS)           # the repeated shape reused its context
-    say("[gpu] server: all requests at once, 4 in flight, reversed arrival")
+    say("[gpu] server: all requests at once, continuous batching (3 slots), reversed arrival")
     mix, info4 = run(4, order=list(reversed(range(len(REQUESTS)))))
     say(f"      {info4}")
     assert info4["peak_inflight"] >= 2
+    assert info4["contexts"] < len(REQUESTS)           # one engine per shape
+    say("[gpu] server: all requests at once, one batched solve each, 4 in flight")
+    con, infoc = run(4, order=list(reversed(range(len(REQUESTS)))), mode="contexts")
+    assert infoc["peak_inflight"] >= 2
+    say("[gpu] server: requests one at a time, continuous batching")
+    cb1, _ = run(1)
     for i in range(len(REQUESTS)):
         st1, s1, lat1, x1, bs = alone[i]
-        st4, s4, lat4, x4, _ = mix[i]
-        say(f"      request {i}: status {st1}/{st4} iters {[a.outer_iters for a in s1]} "
-            f"latency alone {lat1:.1f} ms, mix {lat4:.1f} ms")
-        assert st1 == 0 and st4 == 0
-        assert [a.outer_iters for a in s1] == [a.outer_iters for a in s4]
-        assert np.array_equal(x1, x4)
+        for name, other in (("batching mix", mix), ("contexts mix", con), ("batching alone", cb1)):
+            st4, s4, lat4, x4, _ = other[i]
+            say(f"      request {i} {name}: status {st1}/{st4} iters {[a.outer_iters for a in s1]} "
+                f"latency alone {lat1:.1f} ms, here {lat4:.1f} ms")
+            assert st1 == 0 and st4 == 0
+            assert [a.outer_iters for a in s1] == [a.outer_iters for a in s4]
+            assert np.array_equal(x1, x4)
     # residuals of two of them against the oracle
     for i in (1, 2):
         f, Ls, mf, sub, nrhs, solver = REQUESTS[i]
@@ -117,23 +129,24 @@ def test_server_admission_by_budget_and_oom():
     h.set_mobius(6, *MOB, 0.1)
     h.set_subdomains((4, 4, 4, 4))
     h.set_solver(tol=1e-10, inner_iters=4)
-    est, _ = h.footprint(2)
+    est, _ = h.footprint(3)
     h.close()
     fields = sum(int(np.prod(v[0])) * 4 * 10 * 28 for v in FIELDS.values())
     budget = fields + int(1.3 * est)
-    say(f"[gpu] server: budget {budget} B = fields {fields} + 1.3 x {est}")
-    res, info = run(4, budget=budget)
-    say(f"      {info}")
-    assert info["bytes_peak"] <= budget
-    assert info["peak_inflight"] >= 1
-    for i, (st, stats, lat, x, bs) in res.items():
-        assert st == 0, (i, st)
-    # a budget below any request (every solve needs more than 1 MB of
-    # workspace here): each request fails with OOM, the server keeps running
-    say("[gpu] server: budget below one request")
-    res, info = run(2, budget=fields + (256 << 10))
-    assert all(v[0] == MSPCG_ERR_OOM for v in res.values())
-    assert info["completed"] == len(REQUESTS) and info["inflight"] == 0
+    for mode in ("batching", "contexts"):
+        say(f"[gpu] server ({mode}): budget {budget} B = fields {fields} + 1.3 x {est}")
+        res, info = run(4, budget=budget, mode=mode, slots=3)
+        say(f"      {info}")
+        assert info["bytes_peak"] <= budget
+        assert info["peak_inflight"] >= 1
+        for i, (st, stats, lat, x, bs) in res.items():
+            assert st == 0, (i, st)
+        # a budget below any request (every solve needs more than 1 MB of
+        # workspace here): each request fails with OOM, the server keeps running
+        say(f"[gpu] server ({mode}): budget below one request")
+        res, info = run(2, budget=fields + (256 << 10), mode=mode)
+        assert all(v[0] == MSPCG_ERR_OOM for v in res.values())
+        assert info["completed"] == len(REQUESTS) and info["inflight"] == 0
 
 
 def test_footprint_estimate_covers_the_allocation():
