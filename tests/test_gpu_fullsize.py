@@ -101,7 +101,14 @@ def test_c2_local_operator_and_preconditioner_sampled_subdomains():
 
 
 def test_c2_mspcg_solution_has_oracle_residual_below_tolerance():
+    """The MSPCG solution: the oracle's residual meets the tolerance, and the
+    solution agrees with the oracle's own CG solution to 1e-13
+    (tests/golden/reference_c2.json, 4096 sampled entries) within
+    kappa * tol, kappa(A) from the Lanczos matrix of that CG."""
+    import json
+    import os
     cfg, s, op, til = c2()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "reference_c2.json")))
     b = W.gaussian_source(cfg.dims, cfg.Ls, cfg.src_seed)
     say("[gpu] c2 MSPCG solve (FP32 outer + FP64 reliable updates, FP16 inner)")
     x, st = s.solve(b)
@@ -109,6 +116,11 @@ def test_c2_mspcg_solution_has_oracle_residual_below_tolerance():
     say(f"      {st.outer_iters} outer iterations, library {st.true_rel_resid:.3e}, oracle {res:.3e}")
     assert st.status == 0 and res <= cfg.tol, (st, res)
     assert abs(res - st.true_rel_resid) <= 1e-3 * res
+    d = np.array([x[i0, i1, i2, i3] - complex(re, im) for i0, i1, i2, i3, re, im in ref["samples"]])
+    rms_rel = float(np.sqrt(np.mean(np.abs(d) ** 2)) / (ref["x_norm"] / np.sqrt(x.size)))
+    say(f"      solution against the oracle's: sampled relative error {rms_rel:.2e} "
+        f"(kappa {ref['kappa']:.3g}, kappa * tol = {ref['kappa'] * cfg.tol:.2e})")
+    assert rms_rel < 2 * ref["kappa"] * cfg.tol
 
 
 def _handle(cfg, U):
