@@ -315,11 +315,26 @@ template <typename L> struct Gauge {
   int64_t vh;
 };
 
+// Byte offset of the link record (parity, mu, site); with present false, the
+// end of the array: every read there is out of the buffer's range, returns
+// zeros and moves no data (a hop term that is cut off loads its link without
+// a branch).  The FP32 and FP16 arrays (80 vh records of 80 or 40 bytes)
+// stay below 2^31 bytes under the library's size limits, so that offset plus
+// a record does not wrap.
+template <typename L>
+__device__ __forceinline__ uint32_t link_offset(const Gauge<L>& g, int parity, int mu, uint32_t site, bool present) {
+  using C2 = typename Gauge<L>::c2;
+  constexpr uint32_t rec = 10u * (uint32_t)sizeof(C2);
+  if (sizeof(C2) < 16 && !present) return 8u * (uint32_t)g.vh * rec;
+  return ((uint32_t)(parity * 4 + mu) * (uint32_t)g.vh + site) * rec;
+}
+
 template <typename L, typename T>
-__device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu, uint32_t site, T* u) {
+__device__ __forceinline__ void load_link(const Gauge<L>& g, int parity, int mu, uint32_t site, T* u,
+                                          bool present = true) {
   using C2 = typename Gauge<L>::c2;
   const __amdgpu_buffer_rsrc_t r = make_rsrc(g.data, (uint64_t)80 * (uint64_t)g.vh * sizeof(C2));
-  const uint32_t off = ((uint32_t)(parity * 4 + mu) * (uint32_t)g.vh + site) * 10u * (uint32_t)sizeof(C2);
+  const uint32_t off = link_offset(g, parity, mu, site, present);
   if constexpr (sizeof(C2) == 16) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {

@@ -194,11 +194,13 @@ template <int F> __device__ __forceinline__ uint32_t cmul_word(uint32_t w) {
 
 // The three stored words a lane needs of an FP16 link record: row `a` of U
 // (DAG false) or column `a` (DAG true, for U^dag), one (re, im) half pair per
-// entry.
+// entry.  An absent term (present false) reads past the array: zeros, no
+// data moved.
 template <bool DAG>
-__device__ __forceinline__ u32x4 link_words(const Gauge<__half>& g, int parity, int mu, uint32_t site, int a) {
+__device__ __forceinline__ u32x4 link_words(const Gauge<__half>& g, int parity, int mu, uint32_t site, int a,
+                                            bool present) {
   const __amdgpu_buffer_rsrc_t r = make_rsrc(g.data, (uint64_t)80 * (uint64_t)g.vh * 4u);
-  const uint32_t off = ((uint32_t)(parity * 4 + mu) * (uint32_t)g.vh + site) * 40u;
+  const uint32_t off = link_offset(g, parity, mu, site, present);
   u32x4 w;
   w.x = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (uint32_t)(DAG ? a : 3 * a), 0, 0);
   w.y = __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * (uint32_t)(DAG ? 3 + a : 3 * a + 1), 0, 0);
@@ -349,10 +351,13 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
     constexpr int SB = -SF;
     // A neighbour outside the input region contributes nothing (the cut
     // of eq. diri).  Both terms' loads are issued without a branch (an
-    // absent neighbour reads the region's first site) so that they are in
-    // flight together; only the arithmetic is guarded.  The regions are
-    // ordered by neighbour pattern, so the guard rarely diverges within a
-    // wavefront and a wavefront of rim sites skips most terms.
+    // absent term reads the region's first site, a cached record, and its
+    // link read falls outside the link array: zeros, no data moved) so that
+    // they are in flight together; only the arithmetic is guarded.  The rim
+    // of a region (two thirds of N2, one or two terms present per site) thus
+    // reads no links for its absent terms.  The regions are ordered by neighbour
+    // pattern, so the guard rarely diverges within a wavefront and a
+    // wavefront of rim sites skips most terms.
     const int jf = nb[2 * MU], jb = nb[2 * MU + 1];
     const bool hf = jf >= 0, hb = jb >= 0;
     const int L = lat.ext(MU);
@@ -383,9 +388,9 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
       uint4 qF[3], qB[3];
       T uF[18], uB[18], h[12], gh[12];
       const T scF = load_site_raw16(in, iF, qF);
-      load_link(g, par, MU, lx >> 1, uF);
+      load_link(g, par, MU, lx >> 1, uF, hf);
       const T scB = load_site_raw16(in, iB, qB);
-      load_link(g, 1 - par, MU, lb >> 1, uB);
+      load_link(g, 1 - par, MU, lb >> 1, uB, hb);
       if (hf) {
         project_h<MU, SF>(qF, h);
         su3_mul_half<false>(uF, h, gh);
@@ -399,6 +404,8 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
       return;
     }
     T hF[12], hB[12], uF[18], uB[18], gh[12];
+    // (FP32 and BF16 fields: the links of absent terms are read; cutting
+    // them costs these instances registers they do not have)
     const T scF = load_project<MU, SF>(in, iF, hF);
     load_link(g, par, MU, lx >> 1, uF);
     const T scB = load_project<MU, SB>(in, iB, hB);
@@ -436,14 +443,14 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
     const uint32_t iB = (base_in + (uint32_t)(t.hb ? jb : 0)) * (uint32_t)Ls + (uint32_t)s;
     if constexpr (std::is_same<S, int8_t>::value) {
       t.scF = load_site_v8(in, iF, t.g0, t.g1, t.g2);
-      t.uF = link_words<false>(g, par, MU, lx >> 1, a);
+      t.uF = link_words<false>(g, par, MU, lx >> 1, a, t.hf);
       t.scB = load_site_v8(in, iB, t.k0, t.k1, t.k2);
-      t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a);
+      t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a, t.hb);
     } else {
       t.scF = load_site_v16(in, iF, t.f0, t.f1, t.f2);
-      t.uF = link_words<false>(g, par, MU, lx >> 1, a);
+      t.uF = link_words<false>(g, par, MU, lx >> 1, a, t.hf);
       t.scB = load_site_v16(in, iB, t.b0, t.b1, t.b2);
-      t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a);
+      t.uB = link_words<true>(g, 1 - par, MU, lb >> 1, a, t.hb);
     }
   }
 
@@ -611,25 +618,48 @@ __device__ __forceinline__ Rows tile_rows(int stride, int Ls, int lane, bool f16
   return r;
 }
 
-// one tile: acc += E_chi H[:, site = lane%16, component q]
-__device__ __forceinline__ float4_t mfma_tile16(half4_t a, const float* tile, const Rows& rows, int q, float ics,
-                                                float4_t acc) {
-  half4_t b;
+// Tiles are taken in groups of G consecutive components (G = 4 or 2): a
+// lane reads the G components of one of its rows in one LDS access (16 or 8
+// bytes) and writes its G results of one row the same way.  With the site
+// stride 4 x odd elements, the 8 (b128) or 16 (b64) lanes the LDS serves
+// together sit in distinct site columns, on distinct banks; one component at
+// a time, the 32 lanes of a half-wavefront fall on 8 banks (stride 24 rows,
+// columns 8 apart on the same bank).
+typedef float float2_t __attribute__((ext_vector_type(2)));
+template <int G> using fgrp = typename std::conditional<G == 4, float4_t, float2_t>::type;
+template <int G> using hgrp = typename std::conditional<G == 4, half4_t, half2_t>::type;
+
+// G tiles: acc[j] += E_chi H[:, site = lane%16, component q0 + j]
+template <int G>
+__device__ __forceinline__ void mfma_group16(half4_t a, const float* tile, const Rows& rows, int q0, float ics,
+                                             float4_t* acc) {
+  half4_t b[G];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) b[v] = (_Float16)(tile[rows.o[v] + q] * ics);
-  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) {
+    const fgrp<G> x = *reinterpret_cast<const fgrp<G>*>(tile + rows.o[v] + q0);
+#pragma unroll
+    for (int j = 0; j < G; ++j) b[j][v] = (_Float16)(x[j] * ics);
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[j], acc[j], 0, 0, 0);
 }
 
 // B operand rows of an FP16 tile (the centre field of the FP16-operand
 // epilogue, stored as its values over the largest one of their row)
-// acc += E_chi W[:, site, q] with W(t) = stored(t) x rs[t] (rs = row scale x
-// column ics); rows as tile_rows(.., f16 = true) of the FP16 tile
-__device__ __forceinline__ float4_t mfma_tile16_h(half4_t a, const _Float16* tile, const Rows& rows, int q,
-                                                  const float* rs, float4_t acc) {
-  half4_t b;
+// acc[j] += E_chi W[:, site, q0 + j] with W(t) = stored(t) x rs[t] (rs = row
+// scale x column ics); rows as tile_rows(.., f16 = true) of the FP16 tile
+template <int G>
+__device__ __forceinline__ void mfma_group16_h(half4_t a, const _Float16* tile, const Rows& rows, int q0,
+                                               const float* rs, float4_t* acc) {
+  half4_t b[G];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) b[v] = (_Float16)((float)tile[rows.o[v] + q] * rs[v]);
-  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) {
+    const hgrp<G> x = *reinterpret_cast<const hgrp<G>*>(tile + rows.o[v] + q0);
+#pragma unroll
+    for (int j = 0; j < G; ++j) b[j][v] = (_Float16)((float)x[j] * rs[v]);
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b[j], acc[j], 0, 0, 0);
 }
 
 // A operands for one chirality: f32 path (four k-steps of 16x16x4)
@@ -649,12 +679,42 @@ __device__ __forceinline__ A32 mfma_a32(const float* E, int chi, int Ls, int lan
   return r;
 }
 
-__device__ __forceinline__ float4_t mfma_tile32(const A32& a, const float* tile, const Rows& rows, int q,
-                                                float4_t acc) {
+template <int G>
+__device__ __forceinline__ void mfma_group32(const A32& a, const float* tile, const Rows& rows, int q0,
+                                             float4_t* acc) {
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk)
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], tile[rows.o[kk] + q], acc, 0, 0, 0);
-  return acc;
+  for (int kk = 0; kk < 4; ++kk) {
+    const fgrp<G> x = *reinterpret_cast<const fgrp<G>*>(tile + rows.o[kk] + q0);
+#pragma unroll
+    for (int j = 0; j < G; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.a[kk], x[j], acc[j], 0, 0, 0);
+  }
+}
+
+// the G results of rows 4 (lane / 16) + v of site column lane % 16, scaled
+// by the column scale cs, one G-wide store per row below Ls
+template <int G>
+__device__ __forceinline__ void put_group(float* dst, int stride, int Ls, int lane, int q0, const float4_t* acc,
+                                          float cs) {
+  const int col = lane & 15, g = lane >> 4;
+  float* o = dst + col * stride + q0;
+  auto row = [&](int v) {
+    fgrp<G> y;
+#pragma unroll
+    for (int j = 0; j < G; ++j) y[j] = acc[j][v] * cs;
+    *reinterpret_cast<fgrp<G>*>(o + (4 * g + v) * 24) = y;
+  };
+  if ((Ls & 3) == 0) {
+    // Ls a multiple of 4: a lane's four rows are all valid or all beyond
+    // Ls, so one branch covers every store
+    if (4 * g < Ls) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) row(v);
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * g + v < Ls) row(v);
+  }
 }
 
 // LDS layout of the site kernels:
@@ -876,82 +936,58 @@ k_hop(Geo geo, Field<S> out_b, Field<S> in_b, Field<S> w_b, Field<S> dotf_b, int
         const int t = 4 * g + v;
         rsw[v] = (HOB && e0_live) ? smaxw[col * Ls + (t < Ls ? t : Ls - 1)] * ics : 0.f;
       }
-      auto tile = [&](int chi, int q, const Rows& ra) {
-        float4_t acc = {0.f, 0.f, 0.f, 0.f};
-        if (HO) {
-          if (E1) acc = mfma_tile16(a1[chi], (const float*)tileA, ra, q, ics, acc);
-          if (e0_live) acc = mfma_tile16_h(a0[chi], tileB16, ra, q, rsw, acc);
-        } else {
-          if (E1) acc = mfma_tile32(f1[chi], (const float*)tileA, ra, q, acc);
-          if (e0_live) acc = mfma_tile32(f0[chi], (const float*)tileB, ra, q, acc);
-        }
-        return acc;
-      };
-      auto put = [&](T* dst, int q, const float4_t& acc) {
+      // G tiles of one chirality starting at component q0; ra holds the
+      // lane's row offsets (plus any part of q0 folded into them)
+      auto group = [&](auto gc, int chi, int q0, const Rows& ra, float4_t* acc) {
+        constexpr int G = decltype(gc)::value;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int t = 4 * g + v;
-          if (t < Ls) dst[col * tile_stride(Ls) + t * 24 + q] = (T)(acc[v] * cs);
+        for (int j = 0; j < G; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
+        if (HO) {
+          if (E1) mfma_group16<G>(a1[chi], (const float*)tileA, ra, q0, ics, acc);
+          if (e0_live) mfma_group16_h<G>(a0[chi], tileB16, ra, q0, rsw, acc);
+        } else {
+          if (E1) mfma_group32<G>(f1[chi], (const float*)tileA, ra, q0, acc);
+          if (e0_live) mfma_group32<G>(f0[chi], (const float*)tileB, ra, q0, acc);
         }
       };
-      // With three or more wavefronts each holds at most 8 tiles in
-      // registers, then overwrites the input tile once every wavefront has
-      // read it.  For 3 and 4 wavefronts the tile sequence of a wavefront is
-      // fixed at compile time (component q = wave + j * nwave, chirality
-      // j * nwave >= 12), so every LDS access is one base plus an immediate.
-      auto tiles_fixed = [&](auto nwc) {
+      // With three or four wavefronts each holds 8 (6) tiles in registers,
+      // groups c = wave + i * NW of G = 4 (G = 2) components, then
+      // overwrites the input tile once every wavefront has read it.  The
+      // group sequence of a wavefront is fixed at compile time up to the
+      // wavefront's own offset, so every LDS access is one base plus an
+      // immediate.  Each chirality holds 12 / G groups.
+      auto groups_fixed = [&](auto nwc) {
         constexpr int NW = decltype(nwc)::value;
-        constexpr int NJ = 24 / NW;
+        constexpr int G = NW == 4 ? 2 : 4;
+        constexpr int NG = 24 / (G * NW);
         const int w = __builtin_amdgcn_readfirstlane(wave);
         Rows ra = rA;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ra.o[v] += (uint32_t)w;
-        float4_t accs[NJ];
+        for (int v = 0; v < 4; ++v) ra.o[v] += (uint32_t)(G * w);
+        float4_t accs[NG][G];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) accs[j] = tile(j * NW >= 12 ? 1 : 0, j * NW, ra);
-        __syncthreads();
-        T* ob = tileA + col * tile_stride(Ls) + w;
-        if ((Ls & 3) == 0) {
-          // Ls a multiple of 4: a lane's four rows are all valid or all
-          // beyond Ls, so one branch covers every store
-          if (4 * g < Ls) {
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) ob[(4 * g + v) * 24 + j * NW] = (T)(accs[j][v] * cs);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int t = 4 * g + v;
-              if (t < Ls) ob[t * 24 + j * NW] = (T)(accs[j][v] * cs);
-            }
-          }
+        for (int i = 0; i < NG; ++i) {
+          const int q0 = G * NW * i;   // plus G * w, in ra
+          const int chi = (q0 + G * w) >= 12 ? 1 : 0;
+          group(std::integral_constant<int, G>(), chi, q0, ra, accs[i]);
         }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NG; ++i) put_group<G>(tileA, tile_stride(Ls), Ls, lane, G * (w + NW * i), accs[i], cs);
       };
       T* dst = tileA;
       if (nwave == 3) {
-        tiles_fixed(std::integral_constant<int, 3>());
+        groups_fixed(std::integral_constant<int, 3>());
       } else if (nwave == 4) {
-        tiles_fixed(std::integral_constant<int, 4>());
-      } else if (nwave > 4) {
-        float4_t accs[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int q = wave + j * nwave;
-          if (q < 24) accs[j] = tile(q / 12, q, rA);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int q = wave + j * nwave;
-          if (q < 24) put(tileA, q, accs[j]);
-        }
+        groups_fixed(std::integral_constant<int, 4>());
       } else {
-        for (int q = wave; q < 24; q += nwave) put(tileO, q, tile(q / 12, q, rA));
+        // one or two wavefronts (Ls <= 8): groups of 4 into a tile of their
+        // own, one group in registers at a time
+        for (int c = wave; c < 6; c += nwave) {
+          float4_t acc[4];
+          group(std::integral_constant<int, 4>(), c >= 3 ? 1 : 0, 4 * c, rA, acc);
+          put_group<4>(tileO, tile_stride(Ls), Ls, lane, 4 * c, acc, cs);
+        }
         dst = tileO;
       }
       __syncthreads();

@@ -42,12 +42,17 @@ TOL_HOP = {"fp64": 1e-13, "fp32": 1e-6, "fp16": 1.5e-3, "bf16": 1.2e-2, "int8": 
 
 LATTICES = [
     # dims, Ls : covers a ragged last block (V/2 not a multiple of the block's
-    # sites), odd Ls, the degenerate 2^4 lattice and unequal extents
+    # sites), odd Ls, the degenerate 2^4 lattice and unequal extents; the
+    # MFMA epilogue's one-, two-, three- and four-wavefront schedules (Ls up
+    # to 4, 5..8, 9..12, 13..16), each with an Ls that is not a multiple of 4
     ((4, 4, 4, 4), 4),
     ((6, 4, 2, 8), 5),
     ((2, 2, 2, 2), 3),
     ((8, 8, 8, 8), 8),
     ((4, 2, 6, 4), 12),
+    ((2, 4, 2, 4), 11),
+    ((4, 4, 2, 2), 16),
+    ((2, 2, 4, 2), 14),
 ]
 
 
@@ -192,6 +197,7 @@ SUBS = [
     ((12, 4, 2, 2), 3, (4, 4, 2, 2)),
     ((8, 8, 8, 8), 8, (4, 4, 4, 4)),
     ((8, 4, 4, 8), 12, (4, 4, 4, 4)),   # the benchmark's Ls: 16-bit terms on 4 x 4 x 4 MFMA blocks
+    ((8, 4, 2, 4), 16, (4, 4, 2, 4)),   # four-wavefront epilogue
 ]
 
 
