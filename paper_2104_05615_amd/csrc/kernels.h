@@ -192,10 +192,11 @@ void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_oute
                   int nsub, int Ls, double* partial, const Batch& bt = Batch());
 // alpha_d = rho_d / <p_s, q_s> from the [d][bps] partials pq (SUB_ALPHA, computed
 // by every wavefront), then z_s (+)= alpha_d p_s ; r_s -= alpha_d q_s ;
-// partial |r_s|^2  (first: z_s = alpha_d p_s)
+// partial |r_s|^2  (first: z_s = alpha_d p_s).  last: the k-th step, whose
+// residual nothing reads: z_s only (r_s, q_s untouched, partials zero).
 void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
-                const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
-                const double* pq, double* partial, const Batch& bt = Batch());
+                const FieldPtr& qs, const SubScalars& sc, bool first, bool last, const SubTables& tc, int nsub,
+                int Ls, const double* pq, double* partial, const Batch& bt = Batch());
 // beta_d = |r_s|^2 / rho_d from the [d][bps] partials rr (SUB_BETA, computed by
 // every wavefront; rho_next = |r_s|^2), then p_s = r_s + beta_d p_s ; t0 = E p_s
 void sub_xpay5(hipStream_t st, Prec inner, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& t0,

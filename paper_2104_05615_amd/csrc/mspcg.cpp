@@ -796,7 +796,7 @@ struct mspcg_ctx {
         std::swap(sc.rho, sc.rho_next);
       }
       Asub(st, I, qs, ps, t0, ppap, bt);
-      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, tc, nsub, Ls, ppap, prr, bt);
+      sub_update(st, I, zs, ps, rs, qs, sc, it == 0, it == k - 1, tc, nsub, Ls, ppap, prr, bt);
     }
     sub_prolong(st, O, I, z, zs, r, rold, lat, tc, nsub, Ls, pz1, pz2, bt);
     ev_end(st, ev);

@@ -133,7 +133,7 @@ __device__ __forceinline__ double fused_finish(const double* partial, int bps, i
 
 template <typename I>
 __global__ void __launch_bounds__(256)
-k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, SubScalars sc, int nsub, int first,
+k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, SubScalars sc, int nsub, int first, int last,
              SubTables tc, int Ls, int ns, const double* pq, double* partial, const int* mask) {
   using T = calc_t<I>;
   __shared__ double red[16];
@@ -151,10 +151,8 @@ k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, SubScalars sc, 
   double loc = 0;
   if (c.valid) {
     const T a = (T)alpha_d;
-    T z[24], p[24], r[24], q[24];
+    T z[24], p[24];
     load_site(ps, c.in5, p);
-    load_site(rs, c.in5, r);
-    load_site(qs, c.in5, q);
     if (first) {
 #pragma unroll
       for (int k = 0; k < 24; ++k) z[k] = a * p[k];
@@ -163,13 +161,18 @@ k_sub_update(Field<I> zs, Field<I> ps, Field<I> rs, Field<I> qs, SubScalars sc, 
 #pragma unroll
       for (int k = 0; k < 24; ++k) z[k] += a * p[k];
     }
-#pragma unroll
-    for (int k = 0; k < 24; ++k) {
-      r[k] -= a * q[k];
-      loc += (double)r[k] * (double)r[k];
-    }
     store_site(zs, c.in5, z);
-    store_site(rs, c.in5, r);
+    if (!last) {
+      T r[24], q[24];
+      load_site(rs, c.in5, r);
+      load_site(qs, c.in5, q);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) {
+        r[k] -= a * q[k];
+        loc += (double)r[k] * (double)r[k];
+      }
+      store_site(rs, c.in5, r);
+    }
   }
   const double tot = block_sum(loc, red);
   if (threadIdx.x == 0) partial[c.blk] = tot;
@@ -335,24 +338,24 @@ void sub_restrict(hipStream_t st, Prec outer, Prec inner, const FieldPtr& r_oute
 
 template <typename I>
 static void update_t(hipStream_t st, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs, const FieldPtr& qs,
-                     const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls, const double* pq,
-                     double* partial, const Batch& bt) {
+                     const SubScalars& sc, bool first, bool last, const SubTables& tc, int nsub, int Ls,
+                     const double* pq, double* partial, const Batch& bt) {
   const int ns = c_ns(Ls, zs.prec);
   hipLaunchKernelGGL((k_sub_update<I>), c_grid(nsub, tc, bt), dim3(site_block_threads(ns, Ls)), 0, st, typed<I>(zs),
-                     typed<I>(ps), typed<I>(rs), typed<I>(qs), sc, nsub, first ? 1 : 0, tc, Ls, ns, pq, partial,
-                     bt.mask);
+                     typed<I>(ps), typed<I>(rs), typed<I>(qs), sc, nsub, first ? 1 : 0, last ? 1 : 0, tc, Ls, ns, pq,
+                     partial, bt.mask);
   LAUNCH_CHECK();
 }
 
 void sub_update(hipStream_t st, Prec inner, const FieldPtr& zs, const FieldPtr& ps, const FieldPtr& rs,
-                const FieldPtr& qs, const SubScalars& sc, bool first, const SubTables& tc, int nsub, int Ls,
-                const double* pq, double* partial, const Batch& bt) {
+                const FieldPtr& qs, const SubScalars& sc, bool first, bool last, const SubTables& tc, int nsub,
+                int Ls, const double* pq, double* partial, const Batch& bt) {
   switch (inner) {
-    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
-    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
-    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
-    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
-    case Prec::I8: update_t<int8_t>(st, zs, ps, rs, qs, sc, first, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::F64: update_t<double>(st, zs, ps, rs, qs, sc, first, last, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::F32: update_t<float>(st, zs, ps, rs, qs, sc, first, last, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::F16: update_t<__half>(st, zs, ps, rs, qs, sc, first, last, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::BF16: update_t<__hip_bfloat16>(st, zs, ps, rs, qs, sc, first, last, tc, nsub, Ls, pq, partial, bt); break;
+    case Prec::I8: update_t<int8_t>(st, zs, ps, rs, qs, sc, first, last, tc, nsub, Ls, pq, partial, bt); break;
   }
 }
 

@@ -57,10 +57,12 @@ CONFIGS = {
     # batched multi-RHS on one gauge field
     "c3": Config("c3", (16, 16, 16, 16), 16, 1.5, 0.5, 1.8, 0.005, 0.5, (4, 4, 4, 4), 6,
                  103, 203, nrhs=12, note="16^4 x Ls16, 12 point-smeared sources"),
-    # one GPU's share at production shape; k = 4 inner iterations, the
-    # fastest of k = 4, 5, 6 measured on one GPU (fewer inner steps cost
-    # fewer outer iterations than they save there)
-    "c4": Config("c4", (32, 32, 32, 64), 12, 1.5, 0.5, 1.8, 0.00078, 0.6, (8, 8, 8, 16), 4,
+    # one GPU's share at production shape; k = 3 inner iterations, the
+    # cheapest of the paper's values for this lattice (Table 1: k = 3, 4, 6)
+    # and the fastest of them on one GPU, where an A_s application costs as
+    # much as A and no halo exchange is saved (k = 3, 4, 5, 6: 16.2, 17.1,
+    # 18.8, 20.6 s)
+    "c4": Config("c4", (32, 32, 32, 64), 12, 1.5, 0.5, 1.8, 0.00078, 0.6, (8, 8, 8, 16), 3,
                  104, 204, note="32^3x64 x Ls12, FP32 outer + FP64 reliable updates, FP16 inner on "
-                                "256 subdomains of 8^3x16, k=4"),
+                                "256 subdomains of 8^3x16, k=3"),
 }
