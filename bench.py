@@ -109,7 +109,7 @@ SERVE_FULL = dict(volumes=list(SERVE_VOLUMES), masses=[0.1, 0.01, 0.001], max_rh
 SERVE_SAMPLE = dict(volumes=["8^4x8"], masses=[0.1, 0.01], max_rhs=3)
 
 
-def serve_stream(volumes, masses, max_rhs, nreq=None, seed=105, load=0.75, budget_gb=200, max_inflight=4,
+def serve_stream(volumes, masses, max_rhs, nreq=None, seed=105, load=0.75, budget_gb=140, max_inflight=4,
                  inner_iters=6, mode="batching", slots=8, work_s=None, svc=None):
     """Poisson stream of batched solves through the library's request server.
 
@@ -208,30 +208,37 @@ def serve_stream(volumes, masses, max_rhs, nreq=None, seed=105, load=0.75, budge
                         f"{inf['waiting']} queued")
             results[i] = srv.wait(t)
             del bufs
+            # the request's buffers go back to the device, not to torch's
+            # cache, so that the server's own allocations find the memory
+            torch.cuda.empty_cache()
             ndone[0] += 1
             last = time.perf_counter()
             r = reqs[i]
             log(f"[serve] request {i} ({r[0]}, mf={r[1]}, {r[2]} RHS) done: status {results[i][0]}, "
                 f"latency {results[i][2] / 1e3:.2f}s")
 
-    th = threading.Thread(target=waiter)
+    th = threading.Thread(target=waiter, daemon=True)
     th.start()
     t0 = time.perf_counter()
     t_next = 0.0
-    for i, (name, mf, nrhs) in enumerate(reqs):
-        t_next += gaps[i] / lam
-        b, x = make(name, nrhs, 1000 + i)
-        delay = t0 + t_next - time.perf_counter()
-        if delay > 0:
-            time.sleep(delay)
-        t = submit(name, mf, nrhs, b, x)
+    try:
+        for i, (name, mf, nrhs) in enumerate(reqs):
+            t_next += gaps[i] / lam
+            b, x = make(name, nrhs, 1000 + i)
+            delay = t0 + t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            t = submit(name, mf, nrhs, b, x)
+            with cv:
+                pending.append((i, t, (b, x)))
+                cv.notify()
+    finally:
+        # the requests already submitted finish (the waiter drains them)
+        # even when this loop fails, so the run ends instead of waiting
         with cv:
-            pending.append((i, t, (b, x)))
+            done_submitting[0] = True
             cv.notify()
-    with cv:
-        done_submitting[0] = True
-        cv.notify()
-    th.join()
+        th.join()
     makespan = time.perf_counter() - t0
     info = srv.info()
     srv.close()
@@ -496,7 +503,9 @@ def main():
                     help="serving stream: as many requests as fit this many seconds of sequential work")
     ap.add_argument("--serve-design", default="batching", choices=["batching", "contexts", "both"])
     ap.add_argument("--slots", type=int, default=8, help="RHS slots per shape (continuous batching)")
-    ap.add_argument("--budget-gb", type=int, default=200, help="HBM budget of the request server (GB)")
+    ap.add_argument("--budget-gb", type=int, default=140,
+                    help="HBM budget of the request server (GB); the clients' sources and solutions, up to "
+                         "38 GB per 32^3x64 x Ls12 request of 8 RHS, live beside it")
     ap.add_argument("--serve-sample", type=int, default=10,
                     help="requests of the serving sample in solve mode (0: none)")
     args = ap.parse_args()

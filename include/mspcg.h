@@ -488,7 +488,8 @@ mspcg_status mspcg_server_set_graphs(mspcg_server_t s, int32_t on);
  * stream of its own; a request's right-hand sides queue at its shape's
  * engine and enter slots as earlier ones finish, while the others keep
  * iterating; at most max_inflight engines are busy at once, and an engine
- * holds mspcg_footprint(slots) bytes of the budget; mode 0 -- one resident
+ * opens with as many of the `slots` as the budget holds then (at least one;
+ * it holds mspcg_footprint of that many bytes); mode 0 -- one resident
  * context per shape and a worker thread and stream per admitted request,
  * which runs the request as one batched solve (at most max_inflight at
  * once).  In both modes a right-hand side's solution does not depend on what

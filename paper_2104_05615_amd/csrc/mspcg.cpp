@@ -394,6 +394,9 @@ struct mspcg_ctx {
   bool have_solver = false;
 
   std::map<std::string, std::unique_ptr<DevBuf>> ws;
+  // bumped whenever a workspace is allocated or moves: a captured graph
+  // holds the addresses of the generation it was captured in
+  uint64_t ws_gen = 0;
   // Static-workspace mode (mspcg_apply_device_noalloc): while `arena` is set,
   // buf() hands out views of the device's static workspace, bump-allocated
   // per call, instead of growing the handle's own buffers.
@@ -514,7 +517,9 @@ struct mspcg_ctx {
     }
     auto& p = ws[key];
     if (!p) p.reset(new DevBuf());
+    void* const before = p->p;
     p->ensure(bytes);
+    if (p->p != before) ++ws_gen;
     return *p;
   }
 
@@ -1394,8 +1399,17 @@ struct BatchEngine {
   FieldPtr b64, x64, q64, x, rA, rB, z, p, q, t0;
   FieldPtr* r = &rA;
   FieldPtr* rold = &rB;
-  GraphGuard gg;
-  bool graph_tried = false, graph = false;
+  // Launch width: the kernels of an iteration cover slots [0, w) (a
+  // continuous-batching session keeps w at one past its highest running
+  // slot, so idle slots above it launch no workgroups).  One captured pair
+  // per width, replayed while no workspace has moved since its capture.
+  int w;
+  struct PairGraph {
+    GraphGuard gg;
+    bool tried = false, ok = false, first_done = false;
+    uint64_t gen = 0;
+  };
+  std::map<int, std::unique_ptr<PairGraph>> graphs;
 
   BatchEngine(mspcg_ctx* hh, int nn, hipStream_t s, const std::string& t) : h(hh), n(nn), st(s), tag(t) {
     sp = h->sp;
@@ -1438,7 +1452,7 @@ struct BatchEngine {
     cp.tol = sp.tol;
     cp.delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.0;
     cp.maxiter = sp.maxiter;
-    all.n = act.n = rum.n = bz.n = jn.n = n;
+    set_width(n);
     act.mask = c.active;
     rum.mask = c.ru;
     bz.mask = c.bzero;
@@ -1457,6 +1471,22 @@ struct BatchEngine {
     bytesO = n5 * (int64_t)chunk_bytes(O);
     // every slot idle: no kernel of an iteration touches it
     zero_batched(st, ci, round16((int64_t)(8 * n + 1) * sizeof(int)), Batch());
+  }
+
+  void set_width(int nw) {
+    w = nw;
+    all.n = act.n = rum.n = bz.n = jn.n = nw;
+  }
+
+  // One start-up (no slot joining) and one iteration pair with no slot
+  // taking part, at the full width: every workspace of the engine reaches
+  // its final size here, so no later pair, at any width, moves one.
+  void size_workspaces() {
+    set_width(n);
+    fill_int(st, join, n, 0);
+    start(false);
+    iteration();
+    iteration();
   }
 
   // slot i of a batched field
@@ -1527,18 +1557,25 @@ struct BatchEngine {
   // eagerly (it sizes every workspace); the second is captured and every
   // later one replays the graph (eager if the capture failed: same kernels).
   void run_pair(int flag_slot) {
-    if (graph_tried || !use_graph) {
-      if (graph) HIPCHK(hipGraphLaunch(gg.e, st));
+    std::unique_ptr<PairGraph>& slotp = graphs[w];
+    if (slotp && slotp->ok && slotp->gen != h->ws_gen) {
+      HIPCHK(hipStreamSynchronize(st));   // no replay of the old graph still in flight
+      slotp.reset();
+    }
+    if (!slotp) slotp.reset(new PairGraph());
+    PairGraph& G = *slotp;
+    if (G.tried || !use_graph) {
+      if (G.ok) HIPCHK(hipGraphLaunch(G.gg.e, st));
       else {
         iteration();
         iteration();
       }
-    } else if (!first_done) {
+    } else if (!G.first_done) {
       iteration();
       iteration();
-      first_done = true;
+      G.first_done = true;
     } else {
-      graph_tried = true;
+      G.tried = true;
       std::shared_lock<std::shared_mutex> lk(g_capture_gate);
       bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
       if (ok) {
@@ -1557,17 +1594,18 @@ struct BatchEngine {
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(st, &g);
         ok = ok && ec == hipSuccess && g != nullptr;
-        if (ok) gg.g = g;
+        if (ok) G.gg.g = g;
         else if (g) (void)hipGraphDestroy(g);
       }
       lk.unlock();
-      if (ok) ok = hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0) == hipSuccess;
+      if (ok) ok = hipGraphInstantiate(&G.gg.e, G.gg.g, nullptr, nullptr, 0) == hipSuccess;
       if (!ok) {
         (void)hipGetLastError();
         ++h->capture_fallbacks;
       }
-      graph = ok;
-      if (graph) HIPCHK(hipGraphLaunch(gg.e, st));   // nothing ran during the capture
+      G.ok = ok;
+      G.gen = h->ws_gen;
+      if (G.ok) HIPCHK(hipGraphLaunch(G.gg.e, st));   // nothing ran during the capture
       else {
         iteration();
         iteration();
@@ -1575,7 +1613,6 @@ struct BatchEngine {
     }
     HIPCHK(hipMemcpyAsync(h->h_flag + flag_slot, c.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
   }
-  bool first_done = false;
 
   // statistics of slot i from the control arrays copied to the host
   void stats_of(int i, const std::vector<int>& hi, const std::vector<double>& hd, float ms, double ms_pre,
@@ -1703,6 +1740,7 @@ struct CBSession {
   int* h_status = nullptr;   // pinned copy of the per-slot RhsStatus
   CBSession(mspcg_ctx* hh, int n, hipStream_t s) : h(hh), st(s), slots((size_t)n) {
     E.reset(new BatchEngine(h, n, st, "cb"));
+    E->size_workspaces();
     std::unique_lock<std::shared_mutex> lk(g_capture_gate);
     HIPCHK(hipHostMalloc((void**)&h_status, (size_t)n * sizeof(int), hipHostMallocDefault));
     ++g_cb_sessions;
@@ -1721,8 +1759,12 @@ struct CBSession {
     BatchEngine& B = *E;
     const int n = B.n;
     std::vector<int> joining;
-    for (int i = 0; i < n; ++i)
+    int width = 0;   // one past the highest slot that runs or joins now
+    for (int i = 0; i < n; ++i) {
       if (slots[i].state == SLOT_PENDING) joining.push_back(i);
+      if (slots[i].state == SLOT_PENDING || slots[i].state == SLOT_RUNNING) width = i + 1;
+    }
+    if (width > 0) B.set_width(width);
     if (!joining.empty()) {
       fill_int(st, B.join, n, 0);
       for (int i : joining) {

@@ -240,15 +240,21 @@ struct mspcg_server {
     for (auto& e : engines) active += !e->idle();
     mspcg_t h = new_handle(q->r, st, err);
     if (!h) return nullptr;
+    // An engine opens with as many of the server's slots as the budget
+    // holds (at least one): a large volume runs fewer right-hand sides at
+    // a time, and a request with more right-hand sides than slots runs them
+    // in turn.
+    int n = slots;
     int64_t est = 0, alloc = 0;
     st = mspcg_set_solver(h, &q->r.solver);
-    if (st == MSPCG_OK) st = mspcg_footprint(h, slots, &est, &alloc);
+    if (st == MSPCG_OK) st = mspcg_footprint(h, n, &est, &alloc);
+    while (st == MSPCG_OK && active < max_inflight && used + est > budget && evict_one(nullptr)) {
+    }
+    while (st == MSPCG_OK && n > 1 && used + est > budget) st = mspcg_footprint(h, --n, &est, &alloc);
     if (st != MSPCG_OK) {
       err = mspcg_last_error();
       (void)mspcg_destroy(h);
       return nullptr;
-    }
-    while (active < max_inflight && used + est > budget && evict_one(nullptr)) {
     }
     if (used + est > budget || active >= max_inflight) {
       (void)mspcg_destroy(h);
@@ -256,12 +262,12 @@ struct mspcg_server {
       for (auto& c : ctxs) busy |= c->busy;
       if (!busy) {   // it does not fit even alone
         st = MSPCG_ERR_OOM;
-        err = "an engine of " + std::to_string(slots) + " slots needs " + std::to_string(est) +
+        err = "an engine of one slot needs " + std::to_string(est) +
               " bytes beyond the resident fields; the budget leaves " + std::to_string(budget - used);
       }
       return nullptr;
     }
-    st = mspcg_cb_open(h, slots, nullptr);
+    st = mspcg_cb_open(h, n, nullptr);
     if (st != MSPCG_OK) {
       err = mspcg_last_error();
       (void)mspcg_destroy(h);
@@ -272,7 +278,7 @@ struct mspcg_server {
     e->h = h;
     e->key = key;
     e->bytes = est;
-    e->slots = slots;
+    e->slots = n;
     const Field& f = fields[(size_t)q->r.field];
     e->per = (int64_t)q->r.Ls * ((int64_t)f.dims[0] * f.dims[1] * f.dims[2] * f.dims[3] / 2) * 24;
     used += est;

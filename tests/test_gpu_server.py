@@ -149,6 +149,40 @@ def test_server_admission_by_budget_and_oom():
         assert info["completed"] == len(REQUESTS) and info["inflight"] == 0
 
 
+def test_engine_opens_with_the_slots_the_budget_holds():
+    """A budget that holds one slot of the largest shape but not three:
+    continuous batching still runs every request (that shape's engine opens
+    with fewer slots and its right-hand sides take turns), inside the
+    budget, and every solution meets the oracle's residual."""
+    from paper_2104_05615_amd import MSPCG
+    d, eps, seed = FIELDS["B"]
+    h = MSPCG(d)
+    h.load_gauge(W.gauge_field(d, eps, seed))
+    h.set_mobius(6, *MOB, 0.1)
+    h.set_subdomains((4, 4, 4, 4))
+    h.set_solver(tol=1e-10, inner_iters=4)
+    est1, _ = h.footprint(1)
+    est3, _ = h.footprint(3)
+    h.close()
+    assert est3 > est1
+    fields = sum(int(np.prod(v[0])) * 4 * 10 * 28 for v in FIELDS.values())
+    budget = fields + (est1 + est3) // 2
+    say(f"[gpu] server (batching, 3 slots): budget {budget} B = fields + (one slot {est1} + three {est3}) / 2")
+    res, info = run(4, budget=budget, mode="batching", slots=3)
+    say(f"      {info}")
+    assert info["bytes_peak"] <= budget
+    ops = {}
+    for i, (st, stats, lat, x, bs) in res.items():
+        assert st == 0, (i, st)
+        f, Ls, mf, sub, nrhs, solver = REQUESTS[i]
+        key = (f, Ls, mf)
+        if key not in ops:
+            dims, e, sd = FIELDS[f]
+            ops[key] = oracle.MobiusDWF(W.gauge_field(dims, e, sd), Ls, *MOB, mf)
+        for k in range(nrhs):
+            assert oracle_resid(ops[key], bs[k], x[k]) < 2e-10
+
+
 def test_footprint_estimate_covers_the_allocation():
     import torch
     from paper_2104_05615_amd import MSPCG
