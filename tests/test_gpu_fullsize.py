@@ -1,7 +1,7 @@
 """GPU parity at full size.  The 16^3x32 x Ls12 workload (mf 0.01, links
 exp(0.5 iH)), FP32 outer operator, FP16 preconditioner on 256 subdomains of
 4^3x8 with 6 inner steps, and the benchmark's 32^3x64 x Ls12 workload (mf
-0.00078, links exp(0.6 iH), 256 subdomains of 8^3x16, 4 inner steps), each
+0.00078, links exp(0.6 iH), 256 subdomains of 8^3x16, 3 inner steps), each
 in the launch configuration the benchmark times (default schedules: chunked
 block order of the full-lattice hops, XCD ranges).
 
@@ -190,7 +190,7 @@ def test_c4_operators_full_size():
 
 def test_c4_mspcg_solution_has_oracle_residual_below_tolerance():
     """The benchmark's solve (FP32 outer + FP64 reliable updates, FP16 inner,
-    k = 4) in the benchmark's launch configuration: the oracle's residual of
+    k = 3) in the benchmark's launch configuration: the oracle's residual of
     the returned solution meets the tolerance and equals the library's."""
     cfg, s, op, til = c4()
     b = W.gaussian_source(cfg.dims, cfg.Ls, cfg.src_seed)
