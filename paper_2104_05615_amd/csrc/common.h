@@ -558,9 +558,11 @@ __device__ __forceinline__ void su3_mul_half(const T* u, const T* h, T* g) {
 // share an L2.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
-  const int64_t q = nblocks >> 3, r = nblocks & 7;
-  const int64_t k = b & 7, j = b >> 3;
-  return (k < r) ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j;
+  // 32-bit arithmetic: a grid has fewer than 2^31 workgroups
+  const uint32_t nb = (uint32_t)nblocks, bb = (uint32_t)b;
+  const uint32_t q = nb >> 3, r = nb & 7u;
+  const uint32_t k = bb & 7u, j = bb >> 3;
+  return (int64_t)((k < r) ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j);
 }
 
 // --------------------------------------------------------------------------
@@ -575,6 +577,7 @@ struct FastDiv {
 
 inline FastDiv make_fastdiv(uint32_t d) {
   FastDiv f;
+  if (d == 0) d = 1;   // nothing is ever divided by an empty extent; keep the constants finite
   f.d = d;
   uint32_t s = 0;
   while ((1ull << s) < d) ++s;
@@ -636,6 +639,7 @@ struct SubTables {
   const int* wmap;        // [n_out] index into the centre-field region, -1 = zero; null = same region
   int n_out, n_in, n_w;
   int bps;                // blocks per subdomain
+  FastDiv fbps;           // division by bps (block -> subdomain)
   int sub[4], dims[4], nblk[4];
 };
 

@@ -80,6 +80,7 @@ static HopWork hop_work(int64_t nblk, const Batch& bt, const Sched& sc) {
   wk.order = sc.order;
   wk.xcd = sc.xcd;
   wk.mask = bt.mask;
+  wk.fdiv = make_fastdiv((uint32_t)(sc.order == 0 ? nblk : bt.n));
   return wk;
 }
 

@@ -687,6 +687,7 @@ struct mspcg_ctx {
         t.n_out = nC; t.n_in = nN1; t.n_w = nN2; break;
     }
     t.bps = (t.n_out + ns - 1) / ns;
+    t.fbps = make_fastdiv((uint32_t)t.bps);
     return t;
   }
 

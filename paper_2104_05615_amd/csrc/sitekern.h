@@ -331,7 +331,7 @@ template <typename T, typename LinkT = T, bool MW = false> struct SubGeo {
 
   __device__ __forceinline__ SiteRef locate(int64_t blk, int sl, int ns, int Ls, int s) const {
     SiteRef r;
-    r.d = blk / tb.bps;
+    r.d = (int64_t)tb.fbps.div((uint32_t)blk);   // blocks < 2^31
     const int64_t b = blk - r.d * tb.bps;
     r.site = b * ns + sl;
     r.valid = r.site < tb.n_out;
@@ -756,14 +756,17 @@ struct HopWork {
   int order;         // 0: item = rhs * nblk + blk; 1: item = blk * nrhs + rhs
   int xcd;           // 1: items dealt to XCDs in contiguous ranges (xcd_block)
   const int* mask;   // RHS r skipped when mask[r] == 0 (nullable)
+  FastDiv fdiv;      // division by nblk (order 0) or nrhs (order 1)
+  // 32-bit arithmetic: a launch has fewer than 2^31 items
   __device__ __forceinline__ void decode(int64_t b, int64_t nb, int64_t& blk, int& rhs) const {
-    const int64_t item = xcd ? xcd_block(b, nb) : b;
+    const uint32_t item = (uint32_t)(xcd ? xcd_block(b, nb) : b);
+    const uint32_t q = fdiv.div(item), rem = item - q * fdiv.d;
     if (order == 0) {
-      rhs = (int)(item / nblk);
-      blk = item - (int64_t)rhs * nblk;
+      rhs = (int)q;
+      blk = (int64_t)rem;
     } else {
-      blk = item / nrhs;
-      rhs = (int)(item - blk * nrhs);
+      blk = (int64_t)q;
+      rhs = (int)rem;
     }
   }
 };

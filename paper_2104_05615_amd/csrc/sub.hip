@@ -36,7 +36,7 @@ __device__ __forceinline__ CSite c_site(const SubTables& tc, int ns, int Ls) {
   c.sl = c.inb ? tid / Ls : 0;
   c.s = c.inb ? tid - c.sl * Ls : 0;
   c.blk = xcd_block(blockIdx.x, gridDim.x);
-  c.d = c.blk / tc.bps;
+  c.d = (int64_t)tc.fbps.div((uint32_t)c.blk);   // blocks < 2^31
   c.j = (c.blk - c.d * tc.bps) * ns + c.sl;
   c.valid = c.inb && c.j < tc.n_out;
   c.in5 = (c.d * tc.n_out + c.j) * Ls + c.s;
