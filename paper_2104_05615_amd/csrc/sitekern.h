@@ -146,12 +146,16 @@ template <typename T> struct FullGeo {
     const uint32_t site = (uint32_t)r.site;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
+    // FP32: two directions between register fences, their four terms' loads
+    // in flight together (all eight at once need more registers than the
+    // kernel has and spill); FP64: one direction at a time
+    constexpr bool one = sizeof(T) == 8;
     dir<0, DAG>(in, c, lx, site, s, Ls, acc);
-    pin(acc);
+    if constexpr (one) pin(acc);
     dir<1, DAG>(in, c, lx, site, s, Ls, acc);
     pin(acc);
     dir<2, DAG>(in, c, lx, site, s, Ls, acc);
-    pin(acc);
+    if constexpr (one) pin(acc);
     dir<3, DAG>(in, c, lx, site, s, Ls, acc);
   }
 };
@@ -772,7 +776,13 @@ struct HopWork {
 };
 
 // minimum wavefronts per SIMD the register allocation aims for
-template <typename Geo, typename S, bool HASW> constexpr int hop_waves() { return sizeof(calc_t<S>) == 8 ? 2 : 4; }
+// (the FP32 full-lattice hop may take up to 168 registers for its two
+// directions in flight; the compiler keeps it at four wavefronts)
+template <typename G> struct IsFullF : std::false_type {};
+template <> struct IsFullF<FullGeo<float>> : std::true_type {};
+template <typename Geo, typename S, bool HASW> constexpr int hop_waves() {
+  return sizeof(calc_t<S>) == 8 ? 2 : (IsFullF<Geo>::value && std::is_same<S, float>::value) ? 3 : 4;
+}
 
 template <typename G> struct IsSubGeo : std::false_type {};
 template <typename T, typename L, bool M> struct IsSubGeo<SubGeo<T, L, M>> : std::true_type {};
