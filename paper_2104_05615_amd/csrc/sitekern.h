@@ -146,16 +146,13 @@ template <typename T> struct FullGeo {
     const uint32_t site = (uint32_t)r.site;
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
-    // FP32: two directions between register fences, their four terms' loads
+    // two directions between register fences: their four terms' loads are
     // in flight together (all eight at once need more registers than the
-    // kernel has and spill); FP64: one direction at a time
-    constexpr bool one = sizeof(T) == 8;
+    // kernel has and spill)
     dir<0, DAG>(in, c, lx, site, s, Ls, acc);
-    if constexpr (one) pin(acc);
     dir<1, DAG>(in, c, lx, site, s, Ls, acc);
     pin(acc);
     dir<2, DAG>(in, c, lx, site, s, Ls, acc);
-    if constexpr (one) pin(acc);
     dir<3, DAG>(in, c, lx, site, s, Ls, acc);
   }
 };
