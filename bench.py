@@ -439,6 +439,17 @@ def kernels_bench(args):
         s.set_profiling(False)
         out[f"{op}_{prec}"] = {"outer_hops": n_o, "outer_ms": ms_o, "inner_hops": n_i, "inner_ms": ms_i}
         log(f"[kernels] {op} {prec}: {args.steps} applications")
+    # a few outer iterations of MSPCG and of plain FP32 CG (iteration limit,
+    # not converged): the BLAS-1, restriction, inner update and
+    # prolongation kernels of one solve, for their counters
+    if args.solve_iters > 0:
+        for label, kw in (("mspcg", dict(inner_iters=cfg.inner_iters, inner_prec=inner, outer_prec="fp32")),
+                          ("cg_fp32", dict(outer_prec="fp32", use_precond=False, beta_rule="FR"))):
+            s.set_solver(tol=cfg.tol, maxiter=args.solve_iters, reliable_delta=0.1, **kw)
+            st = s.solve_device(bt.data_ptr(), xt.data_ptr())
+            torch.cuda.synchronize()
+            out[label] = {"outer_iters": st.outer_iters, "status": st.status}
+            log(f"[kernels] {label}: {st.outer_iters} outer iterations (limit {args.solve_iters})")
     print(json.dumps(out), flush=True)
 
 
@@ -483,6 +494,8 @@ def main():
     ap.add_argument("--config", default="c4")
     ap.add_argument("--inner-prec", default=None)
     ap.add_argument("--cg-steps", type=int, default=1)
+    ap.add_argument("--solve-iters", type=int, default=0,
+                    help="kernels mode: also run MSPCG and FP32 CG to this many outer iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "batch", "serve", "kernels", "reduced"])
     ap.add_argument("--mu", type=float, nargs="+", default=[0.05, 0.2], help="mu values of the reduced-Ls scan")
