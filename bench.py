@@ -339,6 +339,7 @@ def reduced_bench(args):
     s.load_gauge(U)
     s.set_mobius(cfg.Ls, cfg.b, cfg.c, cfg.M5, cfg.mf)
     s.set_subdomains(cfg.sub)
+    s.set_log(args.log_every)
     bt = torch.from_numpy(b.view(np.float64).reshape(-1).copy()).cuda()
     xt = torch.empty_like(bt)
     n = bt.numel()

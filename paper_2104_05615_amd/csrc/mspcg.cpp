@@ -2432,6 +2432,14 @@ mspcg_status mspcg_get_schedule(mspcg_t h, int32_t kind, int32_t nrhs, int32_t* 
   });
 }
 
+// the size limits an operator application depends on: region fields in the
+// requested precision only for the operators that use them (A_s and the
+// preconditioner)
+static void check_op_limits(const mspcg_ctx* h, int32_t op, mspcg_prec prec) {
+  const bool regions = h->have_tiling && (op == MSPCG_OP_A_SUB || op == MSPCG_OP_PRECOND);
+  check_limits(h->dims, h->Ls, regions ? h->nsub : 0, regions ? h->nN2 : 0, (int)prec);
+}
+
 mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const double* in, double* out,
                                 void* hip_stream) {
   return guarded([&]() -> mspcg_status {
@@ -2441,7 +2449,7 @@ mspcg_status mspcg_apply_device(mspcg_t h, int32_t op, mspcg_prec prec, const do
     const Prec P = to_prec(prec);
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
-    check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
+    check_op_limits(h, op, prec);
     h->ensure_hip();
     apply_impl(h, op, P, in, out, hip_stream ? (hipStream_t)hip_stream : h->stream);
     return MSPCG_OK;
@@ -2460,7 +2468,7 @@ mspcg_status mspcg_apply_device_noalloc(mspcg_t h, int32_t op, mspcg_prec prec, 
     if (op == MSPCG_OP_PRECOND && h->Lh > 0)
       throw Error(MSPCG_ERR_INVALID_ARG, "the reduced-Ls preconditioner is not available without allocation");
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
-    check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
+    check_op_limits(h, op, prec);
     HIPCHK(hipSetDevice(h->device));
     struct Restore {   // leave the handle as it was, also on an error
       mspcg_ctx* h;
@@ -2489,7 +2497,7 @@ mspcg_status mspcg_apply(mspcg_t h, int32_t op, mspcg_prec prec, const double* i
     const Prec P = to_prec(prec);
     need_state(h);
     std::shared_lock<std::shared_mutex> engine_lock(g_engine_gate);
-    check_limits(h->dims, h->Ls, h->have_tiling ? h->nsub : 0, h->have_tiling ? h->nN2 : 0, (int)prec);
+    check_op_limits(h, op, prec);
     h->ensure_hip();
     const size_t bytes = (size_t)h->n5() * 24 * sizeof(double);
     DevBuf di, dout;

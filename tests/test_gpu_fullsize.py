@@ -189,6 +189,21 @@ def test_c4_operators_full_size():
     sampled_local_checks(s, op, til, psi, subs, cfg.inner_iters)
 
 
+def test_c4_fp64_outer_operator_and_region_limits():
+    """32^3x64 x Ls12 with its 8^3x16 tiling set: the FP64 A (reliable
+    updates, FP64 CG) against the oracle whole; the FP64 A_s, whose region
+    field of 256 subdomains would pass 4 GiB, is refused with INVALID_ARG
+    while the operators without region fields stay available."""
+    from paper_2104_05615_amd import MSPCGError, MSPCG_ERR_INVALID_ARG
+    cfg, s, op, til = c4()
+    psi = W.gaussian_source(cfg.dims, cfg.Ls, 705)
+    say("[gpu] c4 A fp64")
+    check(s.apply("A", "fp64", psi), op.A(psi), 1e-12, "A fp64")
+    with pytest.raises(MSPCGError) as e:
+        s.apply("A_sub", "fp64", psi)
+    assert e.value.status == MSPCG_ERR_INVALID_ARG and "4 GiB" in str(e.value)
+
+
 def test_c4_mspcg_solution_has_oracle_residual_below_tolerance():
     """The benchmark's solve (FP32 outer + FP64 reliable updates, FP16 inner,
     k = 3) in the benchmark's launch configuration: the oracle's residual of
