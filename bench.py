@@ -682,6 +682,19 @@ def main():
             "avg_launch_ms": dom["avg_ms"], "launches_timed": dom["launches_timed"],
             "sample": f"one launch in {PROF_STRIDE} of the stage timed with HIP events over the timed region",
             "algorithmic_bytes_per_launch": dom["algorithmic_bytes"]}
+    # for scale, outside the timed region: what a plain device copy streams here
+    src = torch.empty(1 << 28, device=dev, dtype=torch.float32)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    roof["copy_GBps"] = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    roof["copy_sample"] = "torch device copy of 1 GiB (2 GiB moved), 5 times, events on the current stream"
+    del src, dst
     # MFMA work of the fifth-dimension epilogue: useful dense flops (one real
     # Ls x Ls matrix per chirality on the 12 reals of that chirality: 48 Ls
     # flops per 5D site and matrix; the centre-field matrix of h2 only on the
