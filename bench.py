@@ -524,7 +524,8 @@ def main():
                     help="requests of the serving sample in solve mode (0: none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus N > 1 is not supported"}))
+        print(json.dumps({"error": "bench.py runs on one GPU: the solver has no multi-GPU halo exchange, "
+                                   "so --gpus N > 1 is not supported"}))
         sys.exit(2)
     if args.mode == "batch":
         return batch_bench(args)
