@@ -12,7 +12,7 @@ loop (``hop.c``); all fifth-dimension operators are dense
 ``(4 Ls) x (4 Ls)`` complex matrices in spin x s space built from their
 definitions, applied with a matrix product.
 
-Readings taken where the paper is silent (each is listed in the design doc):
+Readings taken where the paper is silent:
 
 * gamma matrices: chiral basis, gamma_5 = diag(1, 1, -1, -1);
 * periodic boundaries in all four directions;
