@@ -15,7 +15,8 @@ entries).  Every comparison checks the whole-field relative error and the
 largest single-site error, with the bounds of test_gpu_parity (FP32
 operator 1e-6, FP16 operator 3e-3, FP16 preconditioner 3e-2 against the
 exact operator).  The 16^4 x Ls16 workload: A
-whole and a batched solve of its twelve point-smeared sources.
+whole and a batched solve of its twelve point-smeared sources with the FP16
+and with the BF16 preconditioner.
 """
 import sys
 
@@ -136,7 +137,8 @@ def _handle(cfg, U):
 def test_c3_batched_point_sources_full_size():
     """16^4 x Ls16, mf 0.005: A against the oracle whole, and a batched solve
     of all twelve point-smeared sources (one launch per operator for all of
-    them, graph replay), each checked by the oracle's residual."""
+    them, graph replay) with the FP16 and with the BF16 preconditioner, each
+    solution checked by the oracle's residual."""
     import torch
     from workloads.configs import CONFIGS
     cfg = CONFIGS["c3"]
@@ -148,17 +150,20 @@ def test_c3_batched_point_sources_full_size():
     check(s.apply("A", "fp32", psi), op.A(psi), 1e-6, "A fp32")
     B = W.point_smeared_sources(cfg.dims, cfg.Ls, cfg.src_seed, cfg.nrhs)
     n = len(B)
-    say(f"[gpu] c3 batched MSPCG solve, {n} point-smeared sources")
+    assert n == 12
     bt = torch.from_numpy(np.ascontiguousarray(B).view(np.float64).ravel().copy()).cuda()
-    xt = torch.empty_like(bt)
-    st, stats = s.solve_batch_device(n, bt.data_ptr(), xt.data_ptr())
-    torch.cuda.synchronize()
-    xs = xt.cpu().numpy().view(np.complex128).reshape(B.shape)
-    assert st == 0 and n == 12
-    for i in range(n):
-        res = float(np.linalg.norm(B[i] - op.A(xs[i])) / np.linalg.norm(B[i]))
-        say(f"      RHS {i}: {stats[i].outer_iters} outer iterations, oracle residual {res:.3e}")
-        assert stats[i].status == 0 and res <= cfg.tol, (i, res)
+    for inner in ("fp16", "bf16"):
+        say(f"[gpu] c3 batched MSPCG solve, {n} point-smeared sources, {inner} preconditioner")
+        s.set_solver(tol=cfg.tol, maxiter=20000, inner_iters=cfg.inner_iters, inner_prec=inner, outer_prec="fp32")
+        xt = torch.empty_like(bt)
+        st, stats = s.solve_batch_device(n, bt.data_ptr(), xt.data_ptr())
+        torch.cuda.synchronize()
+        xs = xt.cpu().numpy().view(np.complex128).reshape(B.shape)
+        assert st == 0
+        for i in range(n):
+            res = float(np.linalg.norm(B[i] - op.A(xs[i])) / np.linalg.norm(B[i]))
+            say(f"      RHS {i}: {stats[i].outer_iters} outer iterations, oracle residual {res:.3e}")
+            assert stats[i].status == 0 and res <= cfg.tol, (inner, i, res)
     s.close()
 
 
