@@ -134,9 +134,9 @@ mspcg_status mspcg_load_gauge(mspcg_t h, const double* U);
  * mspcg_create together with V < 2^31), an FP64 5D field (checked here) and
  * the largest subdomain region field, nsub * |N2| * Ls * (192, 96, 48 or 24
  * bytes for FP64, FP32, FP16/BF16, INT8 inner storage; checked by
- * set_subdomains, set_solver and every solve and apply, also for the
- * precision an apply names).  A batch of right-hand sides may exceed 4 GiB
- * in total. */
+ * set_subdomains, set_solver and every solve, and by an apply of A_SUB or
+ * PRECOND for the precision it names; the other operators use no region
+ * field).  A batch of right-hand sides may exceed 4 GiB in total. */
 mspcg_status mspcg_set_mobius(mspcg_t h, int32_t Ls, double b, double c, double M5, double mf);
 
 /* Subdomain extents (X, Y, Z, T) of the virtual block decomposition used by the
